@@ -1,0 +1,484 @@
+/*
+ * Cluster-BFS oracle: plain, slow, obviously correct CPU reference.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link,
+ * load or call this file; only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header or table with the
+ * HIP library.
+ *
+ * What it computes (paper, Section 3.1, the subset equation, re-based on the
+ * cluster center as in the star-center storage of Section 5.3): for a graph G
+ * given as CSR and a cluster with ordered sources s_0 (the center), s_1, ...,
+ * s_{k-1}, and an offset radius R,
+ *
+ *     dist[v]            = delta(s_0, v)                (UINT32_MAX if unreachable)
+ *     bit i of mask[o][v] = 1  iff  delta(s_i, v) = delta(s_0, v) + o,  o in [-R, R]
+ *
+ * where delta is the hop distance.  It is that definition written out: one
+ * plain FIFO breadth-first search per source (the sequential form of the
+ * paper's single-source BFS, Appendix A), then a direct encode of the
+ * distances.  A source farther than R from the center in offset at some
+ * reachable vertex (or reaching a vertex the center does not reach) makes the
+ * cluster's status CBFS_E_RADIUS; the Fact and Corollary of Section 3.1 bound
+ * every offset by the source's distance to the center.
+ *
+ * Layouts (all row-major):
+ *   row_ptr[n+1], col[m]            int32 CSR, rows = out-neighbours
+ *   cluster_ptr[C+1], sources[...]  sources of cluster c are
+ *                                   sources[cluster_ptr[c] .. cluster_ptr[c+1])
+ *   dist[C][n]                      uint32
+ *   masks[C][2R+1][n][W]            uint64; source i -> bit (i % 64) of word i/64
+ *   status[C]                       0 or -5 (radius violated)
+ *
+ * Also here: graph cleanup into the CSR the searches run on (drop self-loops,
+ * add reverse arcs, drop duplicate arcs, keep the largest connected component,
+ * relabel in ascending original-id order), the brute-force landmark-labeling query (Algorithm "Framework of
+ * Landmark Labeling", Query: min over landmarks of the two distances), the
+ * same query evaluated from this oracle's own encoded labels by the lowest
+ * non-empty intersection (Section 4.2, answering queries with clustered
+ * landmarks), and a BFS-certificate checker for any encoded output.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_OK 0
+#define OR_E_ARG (-1)
+#define OR_E_RADIUS (-5)
+#define OR_E_NOMEM (-8)
+#define UNREACHED (-1)
+
+static int nthreads_or_default(int32_t nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#else
+    nthreads = 1;
+#endif
+    return nthreads < 1 ? 1 : nthreads;
+}
+
+/* Plain FIFO BFS from src.  dist[v] = hops from src, -1 when unreachable.
+ * queue must hold n entries. */
+static void bfs(int64_t n, const int32_t *row_ptr, const int32_t *col, int32_t src,
+                int32_t *dist, int32_t *queue)
+{
+    for (int64_t v = 0; v < n; v++) dist[v] = UNREACHED;
+    int64_t head = 0, tail = 0;
+    dist[src] = 0;
+    queue[tail++] = src;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; e++) {
+            int32_t v = col[e];
+            if (dist[v] == UNREACHED) {
+                dist[v] = dist[u] + 1;
+                queue[tail++] = v;
+            }
+        }
+    }
+}
+
+int oracle_bfs(int64_t n, const int32_t *row_ptr, const int32_t *col, int32_t src, int32_t *dist)
+{
+    if (n <= 0 || src < 0 || src >= n) return OR_E_ARG;
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!queue) return OR_E_NOMEM;
+    bfs(n, row_ptr, col, src, dist, queue);
+    free(queue);
+    return OR_OK;
+}
+
+/* Distances from a batch of sources, one BFS per source, in parallel over sources.
+ * d[j*n + v] = delta(src[j], v). */
+static int bfs_batch(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                     const int32_t *src, int32_t count, int32_t *d, int nthreads)
+{
+    int failed = 0;
+#pragma omp parallel num_threads(nthreads)
+    {
+        int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        if (!queue) {
+#pragma omp atomic write
+            failed = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int32_t j = 0; j < count; j++) {
+            if (queue) bfs(n, row_ptr, col, src[j], d + (size_t)j * (size_t)n, queue);
+        }
+        free(queue);
+    }
+    return failed ? OR_E_NOMEM : OR_OK;
+}
+
+int oracle_cbfs(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                int32_t num_clusters, const int32_t *cluster_ptr, const int32_t *sources,
+                int32_t R, int32_t W, uint32_t *dist, uint64_t *masks, int32_t *status,
+                int32_t nthreads)
+{
+    if (n <= 0 || num_clusters < 0 || R < 0 || W < 1) return OR_E_ARG;
+    int nt = nthreads_or_default(nthreads);
+    const int64_t P = 2 * (int64_t)R + 1;
+    const int32_t batch = nt;
+    int32_t *d0 = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *db = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * (size_t)batch);
+    if (!d0 || !db) {
+        free(d0);
+        free(db);
+        return OR_E_NOMEM;
+    }
+    int rc = OR_OK;
+    for (int32_t c = 0; c < num_clusters && rc == OR_OK; c++) {
+        const int32_t *S = sources + cluster_ptr[c];
+        const int32_t k = cluster_ptr[c + 1] - cluster_ptr[c];
+        if (k < 1 || k > 64 * W) { rc = OR_E_ARG; break; }
+        uint32_t *dc = dist + (size_t)c * (size_t)n;
+        uint64_t *mc = masks + (size_t)c * (size_t)P * (size_t)n * (size_t)W;
+        memset(mc, 0, sizeof(uint64_t) * (size_t)P * (size_t)n * (size_t)W);
+        int violated = 0;
+
+        /* distance from the center s_0 */
+        rc = bfs_batch(n, row_ptr, col, S, 1, d0, 1);
+        if (rc != OR_OK) break;
+        for (int64_t v = 0; v < n; v++) dc[v] = d0[v] == UNREACHED ? UINT32_MAX : (uint32_t)d0[v];
+
+        /* every source, a batch at a time, then encode its offsets */
+        for (int32_t i0 = 0; i0 < k && rc == OR_OK; i0 += batch) {
+            int32_t cnt = k - i0 < batch ? k - i0 : batch;
+            rc = bfs_batch(n, row_ptr, col, S + i0, cnt, db, nt);
+            if (rc != OR_OK) break;
+#pragma omp parallel for num_threads(nt) schedule(static)
+            for (int64_t v = 0; v < n; v++) {
+                for (int32_t j = 0; j < cnt; j++) {
+                    const int32_t i = i0 + j;
+                    const int32_t di = db[(size_t)j * (size_t)n + (size_t)v];
+                    if (d0[v] == UNREACHED) {
+                        if (di != UNREACHED) {
+#pragma omp atomic write
+                            violated = 1;
+                        }
+                        continue;
+                    }
+                    if (di == UNREACHED) {
+#pragma omp atomic write
+                        violated = 1;
+                        continue;
+                    }
+                    const int32_t off = di - d0[v];
+                    if (off < -R || off > R) {
+#pragma omp atomic write
+                        violated = 1;
+                        continue;
+                    }
+                    mc[((size_t)(off + R) * (size_t)n + (size_t)v) * (size_t)W + (size_t)(i / 64)] |=
+                        (uint64_t)1 << (i % 64);
+                }
+            }
+        }
+        status[c] = violated ? OR_E_RADIUS : OR_OK;
+    }
+    free(d0);
+    free(db);
+    return rc;
+}
+
+/* Landmark-labeling query by brute force: for each pair (s, t),
+ * ans = min over every cluster c and every source x of c of delta(x,s)+delta(x,t),
+ * UINT32_MAX if no landmark reaches both. */
+int oracle_query_landmarks(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                           int32_t num_clusters, const int32_t *cluster_ptr, const int32_t *sources,
+                           int64_t q, const int32_t *qs, const int32_t *qt, uint32_t *ans,
+                           int32_t nthreads)
+{
+    if (n <= 0 || q < 0 || num_clusters < 0) return OR_E_ARG;
+    int nt = nthreads_or_default(nthreads);
+    for (int64_t j = 0; j < q; j++) {
+        if (qs[j] < 0 || qs[j] >= n || qt[j] < 0 || qt[j] >= n) return OR_E_ARG;
+        ans[j] = UINT32_MAX;
+    }
+    const int32_t total = cluster_ptr[num_clusters];
+    int32_t *db = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * (size_t)nt);
+    if (!db) return OR_E_NOMEM;
+    int rc = OR_OK;
+    for (int32_t x0 = 0; x0 < total && rc == OR_OK; x0 += nt) {
+        int32_t cnt = total - x0 < nt ? total - x0 : nt;
+        rc = bfs_batch(n, row_ptr, col, sources + x0, cnt, db, nt);
+        if (rc != OR_OK) break;
+        for (int32_t j = 0; j < cnt; j++) {
+            const int32_t *d = db + (size_t)j * (size_t)n;
+#pragma omp parallel for num_threads(nt) schedule(static)
+            for (int64_t p = 0; p < q; p++) {
+                int32_t a = d[qs[p]], b = d[qt[p]];
+                if (a == UNREACHED || b == UNREACHED) continue;
+                uint32_t val = (uint32_t)(a + b);
+                if (val < ans[p]) ans[p] = val;
+            }
+        }
+    }
+    free(db);
+    return rc;
+}
+
+/* The same query from encoded labels (dist[C][n], masks[C][2R+1][n][1], k <= 64):
+ * per cluster, scan offset pairs (a, b) in increasing order of a + b and stop at
+ * the first non-empty intersection mask[a][s] & mask[b][t]; the candidate is
+ * dist[s] + dist[t] + a + b.  The answer is the minimum over clusters. */
+int oracle_query_labels(int64_t n, int32_t num_clusters, int32_t R, const uint32_t *dist,
+                        const uint64_t *masks, int64_t q, const int32_t *qs, const int32_t *qt,
+                        uint32_t *ans)
+{
+    if (n <= 0 || R < 0 || q < 0) return OR_E_ARG;
+    const int64_t P = 2 * (int64_t)R + 1;
+    for (int64_t p = 0; p < q; p++) {
+        const int32_t s = qs[p], t = qt[p];
+        if (s < 0 || s >= n || t < 0 || t >= n) return OR_E_ARG;
+        uint32_t best = UINT32_MAX;
+        for (int32_t c = 0; c < num_clusters; c++) {
+            const uint32_t ds = dist[(size_t)c * n + s], dt = dist[(size_t)c * n + t];
+            if (ds == UINT32_MAX || dt == UINT32_MAX) continue;
+            const uint64_t *mc = masks + (size_t)c * (size_t)P * (size_t)n;
+            int found = 0;
+            for (int32_t sum = -2 * R; sum <= 2 * R && !found; sum++) {
+                for (int32_t a = -R; a <= R; a++) {
+                    int32_t b = sum - a;
+                    if (b < -R || b > R) continue;
+                    if (mc[(size_t)(a + R) * n + s] & mc[(size_t)(b + R) * n + t]) {
+                        int64_t val = (int64_t)ds + (int64_t)dt + sum;
+                        if ((uint64_t)val < best) best = (uint32_t)val;
+                        found = 1;
+                        break;
+                    }
+                }
+            }
+        }
+        ans[p] = best;
+    }
+    return OR_OK;
+}
+
+/* BFS certificate for one encoded cluster output (no oracle run needed).
+ * With delta_i(v) = dist[v] + offset of bit i at v, the decoded distances are
+ * the true hop distances iff: delta_i(s_i) = 0 and no other vertex is 0; every
+ * arc (u, v) has |delta_i(u) - delta_i(v)| <= 1 (unreached on both ends or on
+ * neither); every reached v != s_i has a neighbour at delta_i(v) - 1.  Each
+ * reached v must carry bit i in exactly one plane; unreached v carry no bits.
+ * Returns the number of violations found (0 = certified), or a negative error. */
+int64_t oracle_certificate(int64_t n, const int32_t *row_ptr, const int32_t *col, int32_t k,
+                           const int32_t *S, int32_t R, int32_t W, const uint32_t *dist,
+                           const uint64_t *masks, int32_t nthreads)
+{
+    if (n <= 0 || k < 1 || k > 64 * W || R < 0) return OR_E_ARG;
+    int nt = nthreads_or_default(nthreads);
+    const int64_t P = 2 * (int64_t)R + 1;
+    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * (size_t)k);
+    if (!d) return OR_E_NOMEM;
+    int64_t bad = 0;
+    /* decode */
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : bad)
+    for (int64_t v = 0; v < n; v++) {
+        for (int32_t i = 0; i < k; i++) {
+            int32_t found = 0, off = 0;
+            for (int64_t p = 0; p < P; p++) {
+                uint64_t w = masks[((size_t)p * n + v) * W + (size_t)(i / 64)];
+                if ((w >> (i % 64)) & 1) {
+                    found++;
+                    off = (int32_t)(p - R);
+                }
+            }
+            if (dist[v] == UINT32_MAX) {
+                if (found) bad++;
+                d[(size_t)i * n + v] = UNREACHED;
+            } else {
+                if (found != 1) bad++;
+                d[(size_t)i * n + v] = (int32_t)dist[v] + off;
+            }
+        }
+    }
+    /* check */
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 1024) reduction(+ : bad)
+    for (int64_t v = 0; v < n; v++) {
+        for (int32_t i = 0; i < k; i++) {
+            const int32_t dv = d[(size_t)i * n + v];
+            if (v == S[i]) {
+                if (dv != 0) bad++;
+            } else if (dv == 0) {
+                bad++;
+            }
+            int has_parent = 0;
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+                const int32_t du = d[(size_t)i * n + col[e]];
+                if ((du == UNREACHED) != (dv == UNREACHED)) {
+                    bad++;
+                    continue;
+                }
+                if (dv == UNREACHED) continue;
+                if (du - dv > 1 || dv - du > 1) bad++;
+                if (du == dv - 1) has_parent = 1;
+            }
+            if (dv > 0 && !has_parent) bad++;
+        }
+    }
+    free(d);
+    return bad;
+}
+
+/* ---------------------------------------------------------------------------
+ * Graph cleanup.  flags: 1 symmetrize, 2 dedup, 4 drop self-loops, 8 keep the
+ * largest connected component (ties: the component holding the smallest
+ * original id).  Kept vertices are relabelled 0..n-1 in ascending original-id
+ * order; each output row is sorted ascending.  The CSR is returned in buffers
+ * allocated here (release with oracle_free).
+ * ------------------------------------------------------------------------- */
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+static int64_t uf_find(int64_t *parent, int64_t x)
+{
+    while (parent[x] != x) {
+        parent[x] = parent[parent[x]];
+        x = parent[x];
+    }
+    return x;
+}
+
+void oracle_free(void *p) { free(p); }
+
+int oracle_clean_csr(int64_t n_in, int64_t num_edges, const int64_t *src, const int64_t *dst,
+                     uint32_t flags, int64_t *old_to_new, int64_t *n_out, int64_t *m_out,
+                     int32_t **row_ptr_out, int32_t **col_out)
+{
+    if (n_in <= 0 || n_in > INT32_MAX || num_edges < 0) return OR_E_ARG;
+    for (int64_t e = 0; e < num_edges; e++)
+        if (src[e] < 0 || src[e] >= n_in || dst[e] < 0 || dst[e] >= n_in) return OR_E_ARG;
+    const int sym = (flags & 1) != 0, dedup = (flags & 2) != 0, noloop = (flags & 4) != 0,
+              lcc = (flags & 8) != 0;
+
+    /* bucket the arcs by tail */
+    int64_t *off = (int64_t *)calloc((size_t)n_in + 1, sizeof(int64_t));
+    if (!off) return OR_E_NOMEM;
+    for (int64_t e = 0; e < num_edges; e++) {
+        if (noloop && src[e] == dst[e]) continue;
+        off[src[e] + 1]++;
+        if (sym) off[dst[e] + 1]++;
+    }
+    for (int64_t v = 0; v < n_in; v++) off[v + 1] += off[v];
+    const int64_t A = off[n_in];
+    int32_t *adj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(A > 0 ? A : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_in);
+    if (!adj || !fill) {
+        free(off);
+        free(adj);
+        free(fill);
+        return OR_E_NOMEM;
+    }
+    memcpy(fill, off, sizeof(int64_t) * (size_t)n_in);
+    for (int64_t e = 0; e < num_edges; e++) {
+        if (noloop && src[e] == dst[e]) continue;
+        adj[fill[src[e]]++] = (int32_t)dst[e];
+        if (sym) adj[fill[dst[e]]++] = (int32_t)src[e];
+    }
+    /* sort (and dedup) every row; fill[v] becomes the row's kept length */
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t v = 0; v < n_in; v++) {
+        int32_t *row = adj + off[v];
+        int64_t len = off[v + 1] - off[v];
+        qsort(row, (size_t)len, sizeof(int32_t), cmp_i32);
+        if (dedup && len > 1) {
+            int64_t w = 1;
+            for (int64_t j = 1; j < len; j++)
+                if (row[j] != row[w - 1]) row[w++] = row[j];
+            len = w;
+        }
+        fill[v] = len;
+    }
+    /* components (union-find over arcs, arcs taken as undirected) */
+    char *keep = (char *)malloc((size_t)n_in);
+    if (!keep) {
+        free(off);
+        free(adj);
+        free(fill);
+        return OR_E_NOMEM;
+    }
+    if (lcc) {
+        int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_in);
+        int64_t *size = (int64_t *)calloc((size_t)n_in, sizeof(int64_t));
+        if (!parent || !size) {
+            free(parent);
+            free(size);
+            free(off);
+            free(adj);
+            free(fill);
+            free(keep);
+            return OR_E_NOMEM;
+        }
+        for (int64_t v = 0; v < n_in; v++) parent[v] = v;
+        for (int64_t v = 0; v < n_in; v++)
+            for (int64_t j = 0; j < fill[v]; j++) {
+                int64_t a = uf_find(parent, v), b = uf_find(parent, adj[off[v] + j]);
+                if (a != b) {
+                    if (a < b) parent[b] = a;
+                    else parent[a] = b;
+                }
+            }
+        for (int64_t v = 0; v < n_in; v++) size[uf_find(parent, v)]++;
+        /* roots are the smallest id of their component (union keeps the smaller
+         * root), so scanning ids upward meets components by smallest id */
+        int64_t best = -1;
+        for (int64_t v = 0; v < n_in; v++)
+            if (parent[v] == v && (best < 0 || size[v] > size[best])) best = v;
+        for (int64_t v = 0; v < n_in; v++) keep[v] = uf_find(parent, v) == best;
+        free(parent);
+        free(size);
+    } else {
+        memset(keep, 1, (size_t)n_in);
+    }
+    int64_t n = 0;
+    for (int64_t v = 0; v < n_in; v++) old_to_new[v] = keep[v] ? n++ : -1;
+    int64_t m = 0;
+    for (int64_t v = 0; v < n_in; v++)
+        if (keep[v])
+            for (int64_t j = 0; j < fill[v]; j++) m += keep[adj[off[v] + j]] ? 1 : 0;
+    if (m > INT32_MAX) {
+        free(off);
+        free(adj);
+        free(fill);
+        free(keep);
+        return OR_E_ARG;
+    }
+    int32_t *rp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int32_t *cl = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    if (!rp || !cl) {
+        free(rp);
+        free(cl);
+        free(off);
+        free(adj);
+        free(fill);
+        free(keep);
+        return OR_E_NOMEM;
+    }
+    int64_t pos = 0, r = 0;
+    rp[0] = 0;
+    for (int64_t v = 0; v < n_in; v++) {
+        if (!keep[v]) continue;
+        for (int64_t j = 0; j < fill[v]; j++) {
+            int32_t u = adj[off[v] + j];
+            if (keep[u]) cl[pos++] = (int32_t)old_to_new[u];
+        }
+        rp[++r] = (int32_t)pos;
+    }
+    free(off);
+    free(adj);
+    free(fill);
+    free(keep);
+    *n_out = n;
+    *m_out = m;
+    *row_ptr_out = rp;
+    *col_out = cl;
+    return OR_OK;
+}

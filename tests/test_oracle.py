@@ -1,0 +1,375 @@
+"""Pins of the CPU oracle against things other than itself (no GPU needed).
+
+* single-source distances against scipy's shortest paths (a library routine);
+* the encoded cluster distance vectors against the definition evaluated on an
+  independent all-pairs distance matrix, against closed forms (path, cycle,
+  complete graph, star, undamaged grid with Manhattan distances) and a
+  hand-worked fixture;
+* invariants from the Fact / Corollary of Section 3.1;
+* the two query oracles against each other, against true distances (one-sided
+  error, Section 4.2) and against the fixture;
+* the BFS certificate against planted mistakes;
+* the oracle's C cleanup against its numpy/scipy form.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import shortest_path
+
+import oracle
+import synth
+
+U32MAX = np.uint32(0xFFFFFFFF)
+
+
+def csr_of(n, edges):
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    return oracle.clean_csr(n, e[:, 0], e[:, 1], flags=7)[:2]
+
+
+def apsp(row_ptr, col):
+    n = row_ptr.size - 1
+    A = sp.csr_matrix((np.ones(col.size), col, row_ptr), shape=(n, n))
+    D = shortest_path(A, method="D", unweighted=True, directed=True)
+    D[np.isinf(D)] = -1
+    return D.astype(np.int64)
+
+
+def encode_from_apsp(D, cluster, R, W=None):
+    """The subset equation re-based on the center, evaluated on a distance matrix."""
+    n = D.shape[0]
+    k = len(cluster)
+    W = W or (k + 63) // 64
+    dist = np.full(n, U32MAX, dtype=np.uint32)
+    masks = np.zeros((2 * R + 1, n, W), dtype=np.uint64)
+    ok = True
+    c = cluster[0]
+    for v in range(n):
+        if D[c, v] < 0:
+            ok &= all(D[s, v] < 0 for s in cluster)
+            continue
+        dist[v] = D[c, v]
+        for i, s in enumerate(cluster):
+            if D[s, v] < 0:
+                ok = False
+                continue
+            o = D[s, v] - D[c, v]
+            if abs(o) > R:
+                ok = False
+                continue
+            masks[o + R, v, i // 64] |= np.uint64(1) << np.uint64(i % 64)
+    return dist, masks, ok
+
+
+def small_graphs():
+    out = []
+    for seed in range(6):
+        out.append(("gnp", synth.random_graph(60, 0.06, seed)))
+        out.append(("tree", synth.random_tree(50, seed)))
+    out.append(("grid", synth.grid_edges(9, 0.2, seed=3)))
+    out.append(("gnp_sparse_disconnected", synth.random_graph(80, 0.015, 7)))
+    return out
+
+
+@pytest.mark.parametrize("name,g", small_graphs())
+def test_bfs_matches_library_shortest_paths(name, g):
+    n, s, d = g
+    rp, col, _ = oracle.clean_csr(n, s, d, flags=7)
+    D = apsp(rp, col)
+    for src in range(0, rp.size - 1, 7):
+        assert np.array_equal(oracle.bfs(rp, col, src), D[src])
+
+
+@pytest.mark.parametrize("name,g", small_graphs())
+def test_cbfs_equals_definition_on_apsp(name, g):
+    n, s, d = g
+    rp, col, _ = oracle.clean_csr(n, s, d, flags=7)
+    D = apsp(rp, col)
+    nv = rp.size - 1
+    rng = np.random.default_rng(11)
+    clusters = []
+    for c in range(nv):  # every vertex as a star center
+        clusters.append(oracle.cluster_around(rp, col, c, 64, 1))
+    for c in rng.choice(nv, size=min(10, nv), replace=False):
+        clusters.append(oracle.cluster_around(rp, col, int(c), 64, 2))
+    for R in (1, 2):
+        cp = np.zeros(len(clusters) + 1, np.int32)
+        cp[1:] = np.cumsum([x.size for x in clusters])
+        dist, masks, status = oracle.cbfs(rp, col, cp, np.concatenate(clusters), R)
+        for ci, cl in enumerate(clusters):
+            ed, em, ok = encode_from_apsp(D, list(cl), R)
+            assert (status[ci] == 0) == ok, (ci, R)
+            if ok:
+                assert np.array_equal(dist[ci], ed)
+                assert np.array_equal(masks[ci], em)
+
+
+def test_path_graph_closed_form():
+    n = 40
+    rp, col = csr_of(n, [(i, i + 1) for i in range(n - 1)])
+    c = 17
+    dist, masks, st = oracle.cbfs(rp, col, [0, 3], [c, c - 1, c + 1], R=1)
+    assert st[0] == 0
+    for v in range(n):
+        assert dist[0, v] == abs(v - c)
+        m = masks[0, :, v, 0]
+        if v > c:      # c+1 (bit 2) is one nearer, c-1 (bit 1) one farther
+            assert list(m) == [0b100, 0b001, 0b010]
+        elif v < c:
+            assert list(m) == [0b010, 0b001, 0b100]
+        else:          # at the center both neighbours are one farther
+            assert list(m) == [0, 0b001, 0b110]
+
+
+def test_cycle_closed_form():
+    n = 31
+    rp, col = csr_of(n, [(i, (i + 1) % n) for i in range(n)])
+    c = 5
+    cl = [c, c - 1, c + 1]
+    dist, masks, st = oracle.cbfs(rp, col, [0, 3], cl, R=1)
+    cyc = lambda a, b: min(abs(a - b), n - abs(a - b))  # noqa: E731
+    for v in range(n):
+        assert dist[0, v] == cyc(c, v)
+        for i, s in enumerate(cl):
+            o = cyc(s, v) - cyc(c, v)
+            assert (masks[0, o + 1, v, 0] >> np.uint64(i)) & np.uint64(1) == 1
+
+
+def test_complete_graph_closed_form():
+    n = 12
+    rp, col = csr_of(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
+    cl = list(range(n))  # center 0 and every other vertex
+    dist, masks, st = oracle.cbfs(rp, col, [0, n], cl, R=1)
+    full = (1 << n) - 1
+    for v in range(n):
+        m = [int(x) for x in masks[0, :, v, 0]]
+        if v == 0:
+            assert dist[0, v] == 0 and m == [0, 1, full ^ 1]
+        else:  # its own bit is one nearer, every other source at the center's distance
+            assert dist[0, v] == 1 and m == [1 << v, full ^ (1 << v), 0]
+
+
+def test_star_closed_form():
+    L = 20
+    rp, col = csr_of(L + 1, [(0, i) for i in range(1, L + 1)])
+    cl = list(range(L + 1))
+    dist, masks, st = oracle.cbfs(rp, col, [0, L + 1], cl, R=1)
+    full = (1 << (L + 1)) - 1
+    for v in range(1, L + 1):
+        m = [int(x) for x in masks[0, :, v, 0]]
+        assert dist[0, v] == 1
+        assert m == [1 << v, 1, full ^ 1 ^ (1 << v)]
+
+
+def test_undamaged_grid_manhattan_radius2():
+    side = 24
+    n, s, d = synth.grid_edges(side, 0.0, seed=0)
+    rp, col, _ = oracle.clean_csr(n, s, d)
+    center = 10 * side + 7
+    cl = oracle.cluster_around(rp, col, center, 64, 2)
+    assert cl.size == 13  # the radius-2 ball of a 4-neighbour grid interior
+    dist, masks, st = oracle.cbfs(rp, col, [0, cl.size], cl, R=2)
+    assert st[0] == 0
+    rr, cc = np.divmod(np.arange(n), side)
+    man = lambda a: np.abs(rr - a // side) + np.abs(cc - a % side)  # noqa: E731
+    assert np.array_equal(dist[0], man(center).astype(np.uint32))
+    for i, src in enumerate(cl):
+        o = man(int(src)) - man(center)
+        bit = (masks[0, o + 2, np.arange(n), 0] >> np.uint64(i)) & np.uint64(1)
+        assert np.all(bit == 1)
+
+
+def test_single_source_reduces_to_bfs():
+    n, s, d = synth.random_graph(70, 0.05, 4)
+    rp, col, _ = oracle.clean_csr(n, s, d, flags=7)
+    for src in (0, 13, 40):
+        dist, masks, st = oracle.cbfs(rp, col, [0, 1], [src], R=1)
+        b = oracle.bfs(rp, col, src)
+        assert np.array_equal(dist[0].astype(np.int64), np.where(b < 0, 0xFFFFFFFF, b.astype(np.int64)))
+        assert np.array_equal(masks[0, 1, :, 0], (b >= 0).astype(np.uint64))
+        assert not masks[0, 0].any() and not masks[0, 2].any()
+
+
+def test_invariants_random():
+    """Fact/Corollary of Section 3.1: offsets bounded by the source's distance to the center;
+    one plane per source per reached vertex; the center is always at offset 0."""
+    n, s, d = synth.rmat_edges(10, 8, seed=3)
+    rp, col, _ = oracle.clean_csr(n, s, d)
+    centers = oracle.top_degree(rp, 6)
+    cp, src = oracle.build_clusters(rp, col, centers, 64, 1)
+    dist, masks, st = oracle.cbfs(rp, col, cp, src, R=1)
+    assert np.all(st == 0)
+    for c in range(cp.size - 1):
+        cl = src[cp[c]:cp[c + 1]]
+        m = masks[c, :, :, 0]
+        assert not np.any(m[0] & m[1]) and not np.any(m[1] & m[2]) and not np.any(m[0] & m[2])
+        full = np.uint64((1 << cl.size) - 1) if cl.size < 64 else np.uint64(2**64 - 1)
+        reach = dist[c] != U32MAX
+        assert np.all((m[0] | m[1] | m[2])[reach] == full)
+        assert np.all((m[1][reach] & np.uint64(1)) == 1)
+        dc = oracle.bfs(rp, col, int(cl[0]))
+        for j, v in enumerate(cl):  # at v = s_j, bit j is at offset -delta(c, s_j)
+            o = -int(dc[v])
+            assert (m[o + 1, v] >> np.uint64(j)) & np.uint64(1) == 1
+
+
+def test_multiword_cluster():
+    n, s, d = synth.rmat_edges(11, 16, seed=5)
+    rp, col, _ = oracle.clean_csr(n, s, d)
+    c = int(oracle.top_degree(rp, 1)[0])
+    cl = oracle.cluster_around(rp, col, c, 150, 1)
+    assert cl.size == 150
+    D = apsp(rp, col)
+    dist, masks, st = oracle.cbfs(rp, col, [0, 150], cl, R=1)
+    assert masks.shape[-1] == 3
+    ed, em, ok = encode_from_apsp(D, list(cl), 1)
+    assert ok and st[0] == 0
+    assert np.array_equal(dist[0], ed) and np.array_equal(masks[0], em)
+
+
+def test_radius_violation_and_unreachable():
+    # path 0-1-2-3 plus a separate edge 4-5
+    rp, col = csr_of(6, [(0, 1), (1, 2), (2, 3), (4, 5)])
+    dist, masks, st = oracle.cbfs(rp, col, [0, 2, 4, 6], [1, 3, 1, 0], R=1)
+    assert st[0] == oracle.E_RADIUS       # source 3 is two hops from center 1
+    assert st[1] == 0
+    assert dist[1, 4] == U32MAX and dist[1, 5] == U32MAX
+    assert not masks[1, :, 4:].any()
+    dist, masks, st = oracle.cbfs(rp, col, [0, 2], [1, 3], R=2)
+    assert st[0] == 0
+    dist, masks, st = oracle.cbfs(rp, col, [0, 2], [1, 4], R=5)  # source unreachable from center
+    assert st[0] == oracle.E_RADIUS
+
+
+def read_fixture(golden_dir):
+    fx = {"vertex": [], "query": []}
+    with open(os.path.join(golden_dir, "hand_example.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if not line:
+                continue
+            key, *rest = line.split()
+            if key == "n":
+                fx["n"] = int(rest[0])
+            elif key == "edges":
+                fx["edges"] = [tuple(int(x) for x in e.split("-")) for e in rest]
+            elif key == "sources":
+                fx["sources"] = [int(x) for x in rest]
+            elif key == "R":
+                fx["R"] = int(rest[0])
+            else:
+                fx[key].append([int(x) for x in rest])
+    return fx
+
+
+def test_hand_worked_fixture(golden_dir):
+    fx = read_fixture(golden_dir)
+    rp, col = csr_of(fx["n"], fx["edges"])
+    S = fx["sources"]
+    dist, masks, st = oracle.cbfs(rp, col, [0, len(S)], S, R=fx["R"])
+    assert st[0] == 0
+    for v, dv, m1, m0, p1 in fx["vertex"]:
+        assert dist[0, v] == dv
+        assert [int(x) for x in masks[0, :, v, 0]] == [m1, m0, p1]
+    qs = np.array([q[0] for q in fx["query"]], np.int32)
+    qt = np.array([q[1] for q in fx["query"]], np.int32)
+    want = np.array([q[2] for q in fx["query"]], np.uint32)
+    truth = np.array([q[3] for q in fx["query"]])
+    assert np.array_equal(oracle.query_landmarks(rp, col, [0, len(S)], S, qs, qt), want)
+    assert np.array_equal(oracle.query_labels(dist, masks, qs, qt), want)
+    D = apsp(rp, col)
+    assert np.array_equal(D[qs, qt], truth)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_query_oracles_agree_and_bound(seed):
+    n, s, d = synth.rmat_edges(10, 8, seed=seed + 20)
+    rp, col, _ = oracle.clean_csr(n, s, d)
+    centers = oracle.top_degree(rp, 5)
+    cp, src = oracle.build_clusters(rp, col, centers, 64, 1)
+    dist, masks, st = oracle.cbfs(rp, col, cp, src, R=1)
+    nv = rp.size - 1
+    qs, qt = synth.query_pairs(nv, 3000, seed)
+    qs[:50] = src[:50]             # some endpoints are landmarks
+    qt[50:60] = qs[50:60]          # s == t
+    a = oracle.query_landmarks(rp, col, cp, src, qs, qt)
+    b = oracle.query_labels(dist, masks, qs, qt)
+    assert np.array_equal(a, b)
+    D = apsp(rp, col)
+    true = D[qs, qt]
+    assert np.all(a.astype(np.int64) >= true)               # one-sided error
+    assert np.array_equal(a[:50].astype(np.int64), true[:50])  # landmark endpoint: exact
+    for j in range(50, 60):                                 # s == t: twice the nearest landmark
+        assert a[j] == 2 * min(D[x, qs[j]] for x in src)
+
+
+def test_query_labels_radius2_matches_bruteforce():
+    n, s, d = synth.grid_edges(20, 0.1, seed=9)
+    rp, col, _ = oracle.clean_csr(n, s, d)
+    nv = rp.size - 1
+    centers = synth.random_centers(nv, 4, 9)
+    cp, src = oracle.build_clusters(rp, col, centers, 64, 2)
+    dist, masks, st = oracle.cbfs(rp, col, cp, src, R=2)
+    assert np.all(st == 0)
+    qs, qt = synth.query_pairs(nv, 2000, 9)
+    assert np.array_equal(oracle.query_landmarks(rp, col, cp, src, qs, qt),
+                          oracle.query_labels(dist, masks, qs, qt))
+
+
+def test_certificate_accepts_oracle_and_rejects_planted_mistakes():
+    n, s, d = synth.rmat_edges(10, 8, seed=8)
+    rp, col, _ = oracle.clean_csr(n, s, d)
+    c = int(oracle.top_degree(rp, 1)[0])
+    cl = oracle.cluster_around(rp, col, c, 64, 1)
+    dist, masks, st = oracle.cbfs(rp, col, [0, cl.size], cl, R=1)
+    assert oracle.certificate(rp, col, cl, 1, dist[0], masks[0]) == 0
+    bad = masks[0].copy()
+    v = 100
+    w = bad[:, v, 0].copy()            # move source 5's bit to a neighbouring plane
+    p = [i for i in range(3) if (w[i] >> np.uint64(5)) & np.uint64(1)][0]
+    bad[p, v, 0] ^= np.uint64(1 << 5)
+    bad[(p + 1) % 3, v, 0] ^= np.uint64(1 << 5)
+    assert oracle.certificate(rp, col, cl, 1, dist[0], bad) > 0
+    bd = dist[0].copy()
+    bd[200] += 1
+    assert oracle.certificate(rp, col, cl, 1, bd, masks[0]) > 0
+
+
+def test_cleanup_c_matches_numpy_and_scipy():
+    for (n, s, d) in [synth.rmat_edges(12, 8, seed=1), synth.grid_edges(40, 0.4, seed=2),
+                      synth.random_graph(200, 0.01, 5)]:
+        for flags in (15, 7, 11, 13, 14, 0):
+            a = oracle.clean_csr(n, s, d, flags)
+            b = oracle.clean_csr_numpy(n, s, d, flags)
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y), flags
+        rp, col, o2n = oracle.clean_csr(n, s, d)
+        nv = rp.size - 1
+        # symmetric, no self-loops, no duplicates, rows ascending
+        A = sp.csr_matrix((np.ones(col.size), col, rp), shape=(nv, nv))
+        assert (A != A.T).nnz == 0 and A.diagonal().sum() == 0 and A.max() == 1
+        assert np.all(np.diff(col)[np.diff(np.repeat(np.arange(nv), np.diff(rp))) == 0] > 0)
+        # relabel preserves order; kept ids form one component
+        kept = np.nonzero(o2n >= 0)[0]
+        assert np.array_equal(o2n[kept], np.arange(kept.size))
+        assert sp.csgraph.connected_components(A)[0] == 1
+
+
+def test_lcc_tie_takes_smallest_id():
+    # two triangles of equal size: {5,6,7} and {1,2,3}; the one holding id 1 wins
+    e = np.array([(5, 6), (6, 7), (7, 5), (1, 2), (2, 3), (3, 1)], np.int64)
+    rp, col, o2n = oracle.clean_csr(9, e[:, 0], e[:, 1])
+    assert list(np.nonzero(o2n >= 0)[0]) == [1, 2, 3]
+
+
+def test_selection_rules():
+    deg_rp = np.array([0, 2, 5, 7, 10, 10], np.int32)  # degrees 2,3,2,3,0
+    assert list(oracle.top_degree(deg_rp, 3)) == [1, 3, 0]
+    n, s, d = synth.grid_edges(10, 0.0, seed=0)
+    rp, col, _ = oracle.clean_csr(n, s, d)
+    cl = oracle.cluster_around(rp, col, 55, 64, 2)
+    assert list(cl) == [55, 35, 44, 45, 46, 53, 54, 56, 57, 64, 65, 66, 75]
+    cl = oracle.cluster_around(rp, col, 55, 5, 2)
+    assert list(cl) == [55, 35, 44, 45, 46]
