@@ -1,0 +1,228 @@
+/*
+ * cbfs.h -- C ABI of the MI355X (gfx950) Cluster-BFS library, libcbfs.so.
+ *
+ * Cluster-BFS (C-BFS; paper Section 3, Algorithm "Cluster-BFS search from S"):
+ * one breadth-first search from a cluster S = {s_0, ..., s_{k-1}} of nearby
+ * sources that yields, for every vertex v, the hop distance from the cluster
+ * center s_0 plus, for each offset o in [-R, R], the bit-subset of sources
+ * whose distance to v is d(s_0, v) + o.  This is the paper's cluster distance
+ * vector (Section 3.1, subset equation) re-based on the center, the storage
+ * the paper uses for star clusters (Section 5.3: a distance and d bit-subsets
+ * per cluster per vertex).  All arithmetic is exact integer arithmetic.
+ *
+ * Conventions
+ *   - Vertex ids are int32 in [0, n).  Graphs are CSR: row_ptr[n+1] and col[m]
+ *     (int32, m < 2^31); row v lists the out-neighbours of v.  The searches
+ *     need a symmetric graph (every arc (u,v) has its reverse (v,u)), which
+ *     cbfs_build_csr produces; the pull direction reads rows as in-neighbours.
+ *   - Source i of a cluster is bit (i % 64) of word (i / 64); source 0 is the
+ *     cluster center.  A cluster has 1..256 sources, all distinct.
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary process memory.  The library never allocates
+ *     device memory: every device buffer, including the workspace, belongs to
+ *     the caller.  Host arrays are read (and host outputs written) before the
+ *     call returns.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Every entry point returns a cbfs_status.  Argument errors are detected on
+ *     the host before anything is enqueued; such a call writes no output.
+ *     CBFS_E_HIP reports a failed HIP call; cbfs_last_error() gives the detail
+ *     for the calling thread.
+ */
+#ifndef CBFS_H
+#define CBFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cbfs_status;
+enum {
+    CBFS_OK = 0,
+    CBFS_E_ARG = -1,              /* null pointer, bad size or bad tuning value      */
+    CBFS_E_RANGE = -2,            /* a vertex id outside [0, n)                      */
+    CBFS_E_DUP_SOURCE = -3,       /* a vertex listed twice in one cluster            */
+    CBFS_E_TOO_MANY_SOURCES = -4, /* a cluster with 0 or more than 256 sources       */
+    CBFS_E_RADIUS = -5,           /* (per cluster) some offset falls outside [-R, R] */
+    CBFS_E_WORKSPACE = -6,        /* workspace or output capacity too small          */
+    CBFS_E_HIP = -7,              /* a HIP runtime call failed                       */
+    CBFS_E_NOMEM = -8             /* host allocation failed                          */
+};
+
+#define CBFS_MAX_SOURCES 256
+#define CBFS_UNREACHED 0xFFFFFFFFu
+
+/* Human-readable name of a status code (static string). */
+const char *cbfs_status_string(cbfs_status s);
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char *cbfs_last_error(void);
+
+/* ------------------------------------------------------------------------ *
+ * Graph ingest (host).  The paper's inputs are undirected graphs (Section 5
+ * setup) and its applications assume them (Section 4).
+ *
+ * Turns an edge list into a cleaned CSR: flags select
+ *   CBFS_CSR_SYMMETRIZE       add the reverse of every arc
+ *   CBFS_CSR_DEDUP            drop repeated arcs
+ *   CBFS_CSR_DROP_SELF_LOOPS  drop arcs (v, v)
+ *   CBFS_CSR_KEEP_LCC         keep only the largest connected component (arcs
+ *                             taken as undirected; ties go to the component
+ *                             holding the smallest input id)
+ * Kept vertices are renumbered 0..n_out-1 in ascending input-id order, and each
+ * row is sorted ascending.
+ *   n_in                   vertex ids in src/dst lie in [0, n_in), n_in < 2^31
+ *   src, dst [num_edges]   host, int64 endpoints
+ *   row_ptr  [n_in + 1]    host output (first n_out+1 entries written)
+ *   col      [col_capacity] host output (first m_out entries written);
+ *                          2*num_edges always suffices
+ *   n_out, m_out           host outputs: vertex and arc counts
+ *   old_to_new [n_in]      host output, nullable: new id or -1 if dropped
+ * Errors: CBFS_E_ARG (null/negative), CBFS_E_RANGE (endpoint out of range),
+ * CBFS_E_WORKSPACE (col_capacity < m_out or m_out >= 2^31), CBFS_E_NOMEM.
+ * ------------------------------------------------------------------------ */
+enum {
+    CBFS_CSR_SYMMETRIZE = 1,
+    CBFS_CSR_DEDUP = 2,
+    CBFS_CSR_DROP_SELF_LOOPS = 4,
+    CBFS_CSR_KEEP_LCC = 8,
+    CBFS_CSR_ALL = 15
+};
+cbfs_status cbfs_build_csr(int64_t n_in, int64_t num_edges, const int64_t *src, const int64_t *dst,
+                           uint32_t flags, int32_t *row_ptr, int32_t *col, int64_t col_capacity,
+                           int64_t *n_out, int64_t *m_out, int64_t *old_to_new);
+
+/* ------------------------------------------------------------------------ *
+ * Cluster selection (host).  Section 4.2 builds clusters around high-degree
+ * centers; the rules here are the ones the seeded workloads use.
+ *
+ * cbfs_top_degree: the `count` vertices of largest degree (row length), ties
+ * by ascending id, written to out[count] in that order.
+ *
+ * cbfs_select_clusters: for each center c (host centers[num_centers]), the
+ * cluster is c followed by the lowest-id vertices at hop distance 1..hops from
+ * c, ascending, k_max sources at most.  Outputs cluster_ptr[num_centers+1]
+ * (host) and sources[sources_capacity] (host); num_centers*k_max suffices.
+ * Errors: CBFS_E_ARG, CBFS_E_RANGE, CBFS_E_TOO_MANY_SOURCES (k_max outside
+ * 1..256), CBFS_E_WORKSPACE (capacity), CBFS_E_NOMEM.
+ * ------------------------------------------------------------------------ */
+cbfs_status cbfs_top_degree(int64_t n, const int32_t *row_ptr, int32_t count, int32_t *out);
+cbfs_status cbfs_select_clusters(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                                 int32_t num_centers, const int32_t *centers, int32_t k_max,
+                                 int32_t hops, int32_t *cluster_ptr, int32_t *sources,
+                                 int64_t sources_capacity);
+
+/* ------------------------------------------------------------------------ *
+ * Cluster-BFS over a batch of clusters (device).
+ *
+ * Input: a graph and clusters with radius R (Algorithm "Cluster-BFS search
+ * from S": a graph and a cluster of diameter d).  Output, for every cluster c
+ * and vertex v (Section 3.1 subset equation, center-relative):
+ *   dist[c][v]            = d(s_0, v), or CBFS_UNREACHED
+ *   masks[c][o + R][v][w] = word w of the set {i : d(s_i, v) = d(s_0, v) + o},
+ *                           o in [-R, R]; all zero where dist is CBFS_UNREACHED
+ *   cluster_status[c]     = CBFS_OK, or CBFS_E_RADIUS when some source of c
+ *                           lies at an offset outside [-R, R] at some vertex
+ *                           (or reaches a vertex the center does not); the
+ *                           outputs of such a cluster are unspecified.
+ * W (words per mask) = ceil(max_c k_c / 64) over the batch.  By the Fact and
+ * Corollary of Section 3.1 every offset is bounded by the source's distance to
+ * the center, so R >= that distance for every source guarantees CBFS_OK on a
+ * symmetric graph.
+ *
+ * The level-synchronous search follows Algorithm "Cluster-BFS search from S":
+ * per round a vertex phase (new bits = next minus seen, first round, subset
+ * write, seen update) and an edge phase in either direction of Algorithm
+ * "EdgeMap" (push with 64-bit atomic OR, or pull with early exit), chosen per
+ * round from the frontier size and degree sum (Appendix A).  Clusters are
+ * packed several to a vertex word group and share one level loop.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;              /* vertices                               */
+    int64_t m;              /* arcs (= row_ptr[n])                    */
+    const int32_t *row_ptr; /* device [n+1]                           */
+    const int32_t *col;     /* device [m]                             */
+} cbfs_csr;
+
+typedef struct {
+    int32_t num_clusters;       /* C >= 1                                          */
+    const int32_t *cluster_ptr; /* host [C+1], cluster_ptr[0] = 0, non-decreasing  */
+    const int32_t *sources;     /* host; cluster c = sources[cluster_ptr[c] ..
+                                   cluster_ptr[c+1]), its first entry the center   */
+    int32_t radius;             /* R >= 0: 2R+1 offset planes                      */
+} cbfs_batch;
+
+enum {
+    CBFS_MODE_AUTO = 0,       /* library's choice                                          */
+    CBFS_MODE_HOST_LOOP = 1,  /* one launch per round, frontier size read back each round  */
+    CBFS_MODE_PERSISTENT = 2  /* one cooperative launch for the whole batch, device-side
+                                 level loop with grid barriers, no host round trips         */
+};
+
+/* Tuning knobs (nullable: all defaults).  No knob changes any output bit. */
+typedef struct {
+    int32_t mode;              /* CBFS_MODE_*                                          */
+    int32_t group_words;       /* words per vertex of a cluster group: 0 = auto, else a
+                                  multiple of W in {1,2,4,8}                           */
+    int32_t concurrent_groups; /* group slots searched side by side: 0 = auto          */
+    int32_t block_size;        /* 0 = auto, else 256                                    */
+    float alpha;               /* pull when |F| + sum deg(F) > m / alpha; 0 = auto;
+                                  < 0 forces push every round                           */
+    float beta;                /* stay pull while |F| > n / beta; 0 = auto              */
+    int32_t force_pull;        /* 1: pull every round (testing)                         */
+    int32_t reserved;
+} cbfs_tuning;
+
+/* Bytes of device workspace cbfs_run_batch needs for these arguments. */
+size_t cbfs_run_batch_workspace_size(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *t);
+
+/*
+ *   dist           device [C][n]          uint32 output
+ *   masks          device [C][2R+1][n][W] uint64 output
+ *   cluster_status device [C]             int32 output
+ *   workspace      device, workspace_bytes >= cbfs_run_batch_workspace_size(...)
+ * Asynchronous on `stream` in CBFS_MODE_PERSISTENT; CBFS_MODE_HOST_LOOP waits
+ * on the stream once per round.  Errors: CBFS_E_ARG, CBFS_E_RANGE,
+ * CBFS_E_DUP_SOURCE, CBFS_E_TOO_MANY_SOURCES, CBFS_E_WORKSPACE (before any
+ * launch); CBFS_E_HIP.
+ */
+cbfs_status cbfs_run_batch(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *t,
+                           uint32_t *dist, uint64_t *masks, int32_t *cluster_status,
+                           void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ *
+ * Landmark-labeling queries over cluster labels (Section 4.2; Algorithm
+ * "Framework of Landmark Labeling", Query).  query(s, t) = min over clusters c
+ * and sources x of c of d(x, s) + d(x, t); per cluster this is found from the
+ * labels by the lowest non-empty intersection of the offset subsets of s and
+ * t.  Only offsets -R..0 are needed: the center alone already gives offset
+ * sum 0.  Requires one mask word per cluster (k <= 64).
+ *
+ * cbfs_labels_pack: cluster-major C-BFS outputs (dist [C][n], masks
+ * [C][2R+1][n][1], device) -> vertex-major labels dist_vm [n][C] and
+ * mask_vm [n][C][R+1] (planes o = -R..0, device), so one query reads two
+ * contiguous rows.
+ *
+ * cbfs_query_batch: ans[j] = query(s[j], t[j]) (device arrays of length q),
+ * CBFS_UNREACHED when no cluster reaches both endpoints.  Vertex ids are not
+ * range-checked on the device: out-of-range ids are the caller's error.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;               /* vertices                        */
+    int32_t num_clusters;    /* C                               */
+    int32_t radius;          /* R                               */
+    const uint32_t *dist_vm; /* device [n][C]                   */
+    const uint64_t *mask_vm; /* device [n][C][R+1]              */
+} cbfs_labels;
+
+cbfs_status cbfs_labels_pack(const uint32_t *dist, const uint64_t *masks, int32_t num_clusters,
+                             int64_t n, int32_t radius, uint32_t *dist_vm, uint64_t *mask_vm,
+                             void *stream);
+cbfs_status cbfs_query_batch(const cbfs_labels *L, int64_t q, const int32_t *s, const int32_t *t,
+                             uint32_t *ans, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CBFS_H */

@@ -1,0 +1,16 @@
+"""MI355X (gfx950) Cluster-BFS: Python binding of libcbfs.so.
+
+Argument marshalling only: every step runs in the C/HIP library declared in
+``include/cbfs.h``.  PyTorch supplies device memory and the stream.  Importing
+works without a GPU; calling a device entry point needs the built library
+(``python -m paper_2410_17226_amd.build``) and a GPU, and raises otherwise.
+"""
+from __future__ import annotations
+
+from ._binding import (  # noqa: F401
+    CBFS_OK, CBFS_E_RADIUS, CBFS_MODE_AUTO, CBFS_MODE_HOST_LOOP, CBFS_MODE_PERSISTENT,
+    CBFS_CSR_ALL, UNREACHED, CbfsError, LIB_PATH, load, exported_symbols,
+    build_csr, top_degree, select_clusters,
+    Tuning, run_batch_workspace_size, run_batch,
+    labels_pack, query_batch, status_string,
+)

@@ -1,0 +1,264 @@
+"""ctypes binding of libcbfs.so (names follow ``include/cbfs.h``)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcbfs.so")
+
+CBFS_OK = 0
+CBFS_E_RADIUS = -5
+CBFS_MODE_AUTO = 0
+CBFS_MODE_HOST_LOOP = 1
+CBFS_MODE_PERSISTENT = 2
+CBFS_CSR_ALL = 15
+UNREACHED = 0xFFFFFFFF
+
+SYMBOLS = [
+    "cbfs_status_string", "cbfs_last_error", "cbfs_build_csr", "cbfs_top_degree",
+    "cbfs_select_clusters", "cbfs_run_batch_workspace_size", "cbfs_run_batch",
+    "cbfs_labels_pack", "cbfs_query_batch",
+]
+
+_lib = None
+
+
+class CbfsError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})" + (f": {detail}" if detail else ""))
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [("num_clusters", ctypes.c_int32), ("cluster_ptr", ctypes.c_void_p),
+                ("sources", ctypes.c_void_p), ("radius", ctypes.c_int32)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("group_words", ctypes.c_int32),
+                ("concurrent_groups", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("alpha", ctypes.c_float), ("beta", ctypes.c_float),
+                ("force_pull", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _Labels(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("num_clusters", ctypes.c_int32), ("radius", ctypes.c_int32),
+                ("dist_vm", ctypes.c_void_p), ("mask_vm", ctypes.c_void_p)]
+
+
+@dataclass
+class Tuning:
+    """Mirror of ``cbfs_tuning``; zero fields mean the library default."""
+    mode: int = 0
+    group_words: int = 0
+    concurrent_groups: int = 0
+    block_size: int = 0
+    alpha: float = 0.0
+    beta: float = 0.0
+    force_pull: int = 0
+
+    def _c(self) -> _Tuning:
+        return _Tuning(self.mode, self.group_words, self.concurrent_groups, self.block_size,
+                       self.alpha, self.beta, self.force_pull, 0)
+
+
+def load():
+    """Load libcbfs.so; raises if it was not built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_17226_amd.build`")
+    # One HIP runtime per process: torch brings its own libamdhip64 (same
+    # soname); loading it first makes libcbfs bind to that copy instead of a
+    # second runtime that would not see the device torch already opened.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+    lib.cbfs_status_string.argtypes = [i32]
+    lib.cbfs_status_string.restype = ctypes.c_char_p
+    lib.cbfs_last_error.argtypes = []
+    lib.cbfs_last_error.restype = ctypes.c_char_p
+    lib.cbfs_build_csr.argtypes = [i64, i64, P, P, u32, P, P, i64, P, P, P]
+    lib.cbfs_build_csr.restype = i32
+    lib.cbfs_top_degree.argtypes = [i64, P, i32, P]
+    lib.cbfs_top_degree.restype = i32
+    lib.cbfs_select_clusters.argtypes = [i64, P, P, i32, P, i32, i32, P, P, i64]
+    lib.cbfs_select_clusters.restype = i32
+    lib.cbfs_run_batch_workspace_size.argtypes = [P, P, P]
+    lib.cbfs_run_batch_workspace_size.restype = sz
+    lib.cbfs_run_batch.argtypes = [P, P, P, P, P, P, P, sz, P]
+    lib.cbfs_run_batch.restype = i32
+    lib.cbfs_labels_pack.argtypes = [P, P, i32, i64, i32, P, P, P]
+    lib.cbfs_labels_pack.restype = i32
+    lib.cbfs_query_batch.argtypes = [P, i64, P, P, P, P]
+    lib.cbfs_query_batch.restype = i32
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names from ``include/cbfs.h`` that the loaded library resolves."""
+    lib = load()
+    return [s for s in SYMBOLS if hasattr(lib, s)]
+
+
+def status_string(status: int) -> str:
+    try:
+        return load().cbfs_status_string(int(status)).decode()
+    except Exception:
+        return str(status)
+
+
+def _check(rc: int, where: str):
+    if rc != CBFS_OK:
+        raise CbfsError(rc, where, load().cbfs_last_error().decode())
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# --------------------------------------------------------------------------- host entry points
+def build_csr(n_in: int, src, dst, flags: int = CBFS_CSR_ALL):
+    """``cbfs_build_csr``: returns (row_ptr int32[n+1], col int32[m], old_to_new int64[n_in])."""
+    src = np.ascontiguousarray(src, dtype=np.int64)
+    dst = np.ascontiguousarray(dst, dtype=np.int64)
+    cap = 2 * src.size
+    row_ptr = np.empty(int(n_in) + 1, dtype=np.int32)
+    col = np.empty(max(1, cap), dtype=np.int32)
+    old_to_new = np.empty(int(n_in), dtype=np.int64)
+    n_out, m_out = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().cbfs_build_csr(int(n_in), src.size, _np_ptr(src), _np_ptr(dst), int(flags),
+                                 _np_ptr(row_ptr), _np_ptr(col), cap, ctypes.byref(n_out),
+                                 ctypes.byref(m_out), _np_ptr(old_to_new)), "cbfs_build_csr")
+    n, m = n_out.value, m_out.value
+    return row_ptr[: n + 1].copy(), col[:m].copy(), old_to_new
+
+
+def top_degree(row_ptr, count: int) -> np.ndarray:
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    out = np.empty(int(count), dtype=np.int32)
+    _check(load().cbfs_top_degree(row_ptr.size - 1, _np_ptr(row_ptr), int(count), _np_ptr(out)),
+           "cbfs_top_degree")
+    return out
+
+
+def select_clusters(row_ptr, col, centers, k_max: int, hops: int):
+    """``cbfs_select_clusters``: returns (cluster_ptr int32[C+1], sources int32[...])."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    centers = np.ascontiguousarray(centers, dtype=np.int32)
+    cptr = np.empty(centers.size + 1, dtype=np.int32)
+    cap = max(1, centers.size * int(k_max))
+    src = np.empty(cap, dtype=np.int32)
+    _check(load().cbfs_select_clusters(row_ptr.size - 1, _np_ptr(row_ptr), _np_ptr(col), centers.size,
+                                       _np_ptr(centers), int(k_max), int(hops), _np_ptr(cptr),
+                                       _np_ptr(src), cap), "cbfs_select_clusters")
+    return cptr, src[: cptr[-1]].copy()
+
+
+# --------------------------------------------------------------------------- device entry points
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, tuning):
+    cluster_ptr = np.ascontiguousarray(cluster_ptr, dtype=np.int32)
+    sources = np.ascontiguousarray(sources, dtype=np.int32)
+    g = _Csr(row_ptr_d.numel() - 1, col_d.numel(), row_ptr_d.data_ptr(), col_d.data_ptr())
+    b = _Batch(cluster_ptr.size - 1, _np_ptr(cluster_ptr), _np_ptr(sources), int(R))
+    t = tuning._c() if tuning is not None else None
+    return g, b, t, cluster_ptr, sources
+
+
+def run_batch_workspace_size(row_ptr_d, col_d, cluster_ptr, sources, R: int, tuning: Tuning | None = None) -> int:
+    g, b, t, _keep1, _keep2 = _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, tuning)
+    return int(load().cbfs_run_batch_workspace_size(ctypes.byref(g), ctypes.byref(b),
+                                                    ctypes.byref(t) if t is not None else None))
+
+
+def words_for(cluster_ptr) -> int:
+    k = np.diff(np.asarray(cluster_ptr, dtype=np.int64))
+    return int((int(k.max()) + 63) // 64)
+
+
+def run_batch(row_ptr_d, col_d, cluster_ptr, sources, R: int, tuning: Tuning | None = None,
+              out=None, workspace=None, stream=None):
+    """``cbfs_run_batch`` on device CSR tensors (int32).
+
+    Returns ``(dist, masks, status)`` as torch tensors on the graph's device:
+    dist int32[C][n] (bit pattern of uint32), masks int64[C][2R+1][n][W] (bit
+    pattern of uint64), status int32[C].  ``out`` may pass preallocated tensors
+    of those shapes, ``workspace`` a uint8 tensor of at least the required size.
+    """
+    torch = _torch()
+    lib = load()
+    g, b, t, cptr, srcs = _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, tuning)
+    C = cptr.size - 1
+    n = row_ptr_d.numel() - 1
+    W = words_for(cptr)
+    dev = row_ptr_d.device
+    if out is None:
+        dist = torch.empty((C, n), dtype=torch.int32, device=dev)
+        masks = torch.empty((C, 2 * R + 1, n, W), dtype=torch.int64, device=dev)
+        status = torch.empty(C, dtype=torch.int32, device=dev)
+    else:
+        dist, masks, status = out
+    need = int(lib.cbfs_run_batch_workspace_size(ctypes.byref(g), ctypes.byref(b),
+                                                 ctypes.byref(t) if t is not None else None))
+    if need == 0:
+        # let the library report the argument error
+        need = 1
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    rc = lib.cbfs_run_batch(ctypes.byref(g), ctypes.byref(b), ctypes.byref(t) if t is not None else None,
+                            _dptr(dist), _dptr(masks), _dptr(status), _dptr(workspace),
+                            workspace.numel(), _stream_ptr(stream))
+    _check(rc, "cbfs_run_batch")
+    return dist, masks, status
+
+
+def labels_pack(dist, masks, R: int, stream=None):
+    """``cbfs_labels_pack``: vertex-major labels (dist_vm int32[n][C], mask_vm int64[n][C][R+1])."""
+    torch = _torch()
+    C, P, n, W = masks.shape
+    if W != 1:
+        raise ValueError("labels need one mask word per cluster")
+    dist_vm = torch.empty((n, C), dtype=torch.int32, device=masks.device)
+    mask_vm = torch.empty((n, C, R + 1), dtype=torch.int64, device=masks.device)
+    _check(load().cbfs_labels_pack(_dptr(dist), _dptr(masks), C, n, int(R), _dptr(dist_vm), _dptr(mask_vm),
+                                   _stream_ptr(stream)), "cbfs_labels_pack")
+    return dist_vm, mask_vm
+
+
+def query_batch(dist_vm, mask_vm, R: int, s, t, out=None, stream=None):
+    """``cbfs_query_batch`` for device int32 tensors s, t; returns int32 answers (uint32 bits)."""
+    torch = _torch()
+    n, C = dist_vm.shape
+    q = s.numel()
+    ans = out if out is not None else torch.empty(q, dtype=torch.int32, device=s.device)
+    L = _Labels(n, C, int(R), dist_vm.data_ptr(), mask_vm.data_ptr())
+    _check(load().cbfs_query_batch(ctypes.byref(L), q, _dptr(s), _dptr(t), _dptr(ans), _stream_ptr(stream)),
+           "cbfs_query_batch")
+    return ans

@@ -1,0 +1,361 @@
+// Device-side building blocks of the Cluster-BFS level loop (gfx950, wave64).
+//
+// State of one cluster group (several clusters packed into W 64-bit words per
+// vertex; cluster j of the group owns words [j*WC, (j+1)*WC)):
+//   A, B   [n][W]  the paper's S_next / "seen so far" arrays, double-buffered:
+//                  in round i, cur = (i even ? A : B) holds Seen_i(v), the set
+//                  of sources within distance i of v, complete for every v, and
+//                  nxt (the other buffer) accumulates Seen_{i+1}(v).
+//   seen   [n][W]  Seen_{i-1}(v): lets the vertex phase form the new bits
+//                  Seen_i \ Seen_{i-1} while other threads already OR round-i
+//                  contributions into nxt.
+//   queue  2 x [cap] int64 frontier entries (piece << 32 | vertex); a vertex of
+//                  degree deg occupies max(1, ceil(deg / PIECE)) pieces so that
+//                  no work item carries more than PIECE arcs.
+//   bits   3 x [ceil(n/64)] frontier membership bitmaps; round i reads bits[i%3],
+//                  fills bits[(i+1)%3] and clears bits[(i+2)%3].
+//   ctr    3 x 4 counters per rotation: pieces, vertices, degree sum, spare.
+//
+// Invariant (Algorithm "Cluster-BFS search from S", Section 3.2): after the
+// vertex phase of round i, Seen_i(u) = {s : d(s,u) <= i}; the edge phase makes
+// nxt(v) = Seen_i(v) | OR_{u in N(v)} Seen_i(u) = Seen_{i+1}(v), and v joins
+// F_{i+1} iff that adds a bit.  A vertex whose set is full (all sources) is
+// finished: it can receive nothing more.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cbfs {
+
+constexpr int BLOCK = 256;          // threads per block (4 waves of 64)
+constexpr int WAVES = BLOCK / 64;
+constexpr int PIECE = 256;          // max arcs per frontier work item (push)
+constexpr int TILE_ITEMS = 2048;    // merge-path items (rows + arcs) per pull block
+constexpr int IPT = TILE_ITEMS / BLOCK;
+constexpr int STAGE_CAP = 1024;     // LDS frontier staging capacity per block
+constexpr int MAX_W = 8;            // max words per vertex in a group
+constexpr uint32_t UNREACHED = 0xFFFFFFFFu;
+constexpr int32_t E_RADIUS = -5;
+
+struct GraphArgs {
+    int64_t n, m;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const int32_t *tile_row;   // [ntiles+1] merge-path row coordinate of each pull tile
+    const int32_t *tile_edge;  // [ntiles+1] merge-path arc coordinate of each pull tile
+    int32_t ntiles;
+};
+
+struct SlotArgs {
+    uint64_t *A, *B, *seen;
+    int64_t *q0, *q1;
+    uint64_t *bits0, *bits1, *bits2;
+    unsigned long long *ctr;  // [3][4]
+    int64_t nwords;           // bitmap words
+};
+
+struct GroupDesc {
+    int32_t c0;               // global index of the group's first cluster
+    int32_t nc;               // clusters in the group
+    uint64_t full[MAX_W];     // per word: bits of sources present
+};
+
+struct OutArgs {
+    uint32_t *dist;           // [C][n]
+    uint64_t *masks;          // [C][P][n][WC]
+    int32_t *status;          // [C]
+    int32_t R;
+};
+
+__device__ __forceinline__ uint64_t *cur_buf(const SlotArgs &s, int round) { return (round & 1) ? s.B : s.A; }
+__device__ __forceinline__ uint64_t *nxt_buf(const SlotArgs &s, int round) { return (round & 1) ? s.A : s.B; }
+__device__ __forceinline__ int64_t *q_buf(const SlotArgs &s, int round) { return (round & 1) ? s.q1 : s.q0; }
+__device__ __forceinline__ uint64_t *bits_buf(const SlotArgs &s, int r3)
+{
+    return r3 == 0 ? s.bits0 : (r3 == 1 ? s.bits1 : s.bits2);
+}
+__device__ __forceinline__ unsigned long long *ctr_buf(const SlotArgs &s, int round) { return s.ctr + 4 * (round % 3); }
+
+__device__ __forceinline__ unsigned long long or64(uint64_t *p, uint64_t v)
+{
+    return atomicOr(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(v));
+}
+
+template <int W>
+__device__ __forceinline__ void load_words(const uint64_t *p, uint64_t (&x)[W])
+{
+    if constexpr (W % 2 == 1) {
+#pragma unroll
+        for (int w = 0; w < W; w++) x[w] = p[w];
+    } else {
+#pragma unroll
+        for (int w = 0; w < W; w += 2) {
+            ulonglong2 t = *reinterpret_cast<const ulonglong2 *>(p + w);
+            x[w] = t.x;
+            x[w + 1] = t.y;
+        }
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void store_words(uint64_t *p, const uint64_t (&x)[W])
+{
+    if constexpr (W % 2 == 1) {
+#pragma unroll
+        for (int w = 0; w < W; w++) p[w] = x[w];
+    } else {
+#pragma unroll
+        for (int w = 0; w < W; w += 2) {
+            ulonglong2 t;
+            t.x = x[w];
+            t.y = x[w + 1];
+            *reinterpret_cast<ulonglong2 *>(p + w) = t;
+        }
+    }
+}
+
+__device__ __forceinline__ int pieces_of(int deg) { return deg > PIECE ? (deg + PIECE - 1) / PIECE : 1; }
+
+// ---------------------------------------------------------------------------
+// Output encoding for one cluster at vertex v, round i (the vertex phase's
+// "S_u[i - Delta_u] <- S_new" of Algorithm "Cluster-BFS search from S",
+// re-based on the center).  prev = cluster bits seen before round i, nw =
+// bits new in round i.  The center is bit 0 of the cluster's first word.
+//   - center already seen (its round d is in dist): new bits sit at offset i-d.
+//   - center new now: d = i; bits seen earlier sit at negative offsets.  For
+//     R = 1 all of them are at -1 and the still-missing bits must arrive at
+//     +1, so all three planes are written now; for R >= 2 the pre-center
+//     rounds were stashed in planes 0..R-1 (min-relative) and are shifted
+//     into place, and the positive planes are cleared for later rounds.
+//   - center not yet seen: dist holds the first round Delta_c any bit of the
+//     cluster arrived; for R >= 2 the bits are stashed at plane i - Delta_c.
+// Any bit whose offset leaves [-R, R] marks the cluster CBFS_E_RADIUS.
+// ---------------------------------------------------------------------------
+template <int WC>
+__device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_t c, int32_t v,
+                                             int32_t i, const uint64_t *prev, const uint64_t *nw,
+                                             const uint64_t *full)
+{
+    uint64_t any_new = 0, any_prev = 0;
+#pragma unroll
+    for (int x = 0; x < WC; x++) {
+        any_new |= nw[x];
+        any_prev |= prev[x];
+    }
+    if (!any_new) return;
+    const int32_t R = o.R;
+    const int64_t P = 2 * (int64_t)R + 1;
+    uint32_t *dslot = o.dist + (size_t)c * (size_t)n + (size_t)v;
+    auto plane = [&](int64_t p) { return o.masks + (((size_t)c * P + (size_t)p) * (size_t)n + (size_t)v) * WC; };
+    auto put = [&](int64_t p, const uint64_t *val) {
+        uint64_t *dst = plane(p);
+#pragma unroll
+        for (int x = 0; x < WC; x++) dst[x] = val[x];
+    };
+    auto put_zero = [&](int64_t p) {
+        uint64_t *dst = plane(p);
+#pragma unroll
+        for (int x = 0; x < WC; x++) dst[x] = 0;
+    };
+    auto violate = [&]() { atomicExch(o.status + c, E_RADIUS); };
+
+    if (prev[0] & 1ull) {
+        const int32_t k = i - (int32_t)(*dslot);
+        if (k < 1 || k > R) {
+            violate();
+        } else if (R > 1) {
+            put(R + k, nw);
+        }
+        return;
+    }
+    if (nw[0] & 1ull) {
+        const int32_t jc = any_prev ? i - (int32_t)(*dslot) : 0;
+        if (jc < 0 || jc > R) {
+            violate();
+            return;
+        }
+        *dslot = (uint32_t)i;
+        if (R == 1) {
+            uint64_t rest[WC];
+#pragma unroll
+            for (int x = 0; x < WC; x++) rest[x] = full[x] & ~(prev[x] | nw[x]);
+            put(0, prev);
+            put(1, nw);
+            put(2, rest);
+        } else {
+            const int32_t s = R - jc;
+            for (int32_t j = jc - 1; j >= 0; j--) {
+                uint64_t tmp[WC];
+                const uint64_t *src = plane(j);
+#pragma unroll
+                for (int x = 0; x < WC; x++) tmp[x] = src[x];
+                put(j + s, tmp);
+            }
+            for (int32_t p = 0; p < s; p++) put_zero(p);
+            put(R, nw);
+            for (int32_t p = R + 1; p <= 2 * R; p++) put_zero(p);
+        }
+        return;
+    }
+    // center not reached yet
+    int32_t j = 0;
+    if (!any_prev) {
+        *dslot = (uint32_t)i;
+    } else {
+        j = i - (int32_t)(*dslot);
+    }
+    if (j < 0 || j >= R) {
+        violate();
+        return;
+    }
+    if (R > 1) {
+        put(j, nw);
+        if (j == 0)
+            for (int32_t p = 1; p < R; p++) put_zero(p);
+    }
+}
+
+// Vertex phase for u in F_i (lines computing S_new, Delta_u, the subset write
+// and the seen update): cu = Seen_i(u).  nxt(u) receives the new bits so that
+// nxt(u) covers Seen_i(u) by the end of the round.
+template <int W, int WC>
+__device__ __forceinline__ void vertex_phase(const SlotArgs &s, const GroupDesc &g, const OutArgs &o,
+                                             int64_t n, int32_t round, int32_t u, const uint64_t (&cu)[W])
+{
+    uint64_t sv[W], nw[W];
+    load_words<W>(s.seen + (size_t)u * W, sv);
+    bool any = false;
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        nw[w] = cu[w] & ~sv[w];
+        any |= nw[w] != 0;
+    }
+    if (!any) return;
+    store_words<W>(s.seen + (size_t)u * W, cu);
+    uint64_t *nx = nxt_buf(s, round) + (size_t)u * W;
+#pragma unroll
+    for (int w = 0; w < W; w++)
+        if (nw[w]) or64(nx + w, nw[w]);
+#pragma unroll
+    for (int j = 0; j < W / WC; j++)
+        if (j < g.nc) emit_cluster<WC>(o, n, g.c0 + j, u, round, sv + j * WC, nw + j * WC, g.full + j * WC);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged frontier queue: claimed vertices are collected in LDS and
+// appended to the global queue with one atomic per flush, expanded into their
+// PIECE-sized work items.
+// ---------------------------------------------------------------------------
+struct Stager {
+    int32_t v[STAGE_CAP];
+    int32_t deg[STAGE_CAP];
+    int32_t poff[STAGE_CAP];
+    int32_t count;
+    int32_t pieces;
+    unsigned long long degsum;
+    long long base;
+};
+
+__device__ __forceinline__ void stager_init(Stager &st)
+{
+    if (threadIdx.x == 0) {
+        st.count = 0;
+        st.pieces = 0;
+        st.degsum = 0;
+    }
+}
+
+__device__ __forceinline__ void stager_push(Stager &st, int32_t v, int32_t deg)
+{
+    const int slot = atomicAdd(&st.count, 1);
+    const int po = atomicAdd(&st.pieces, pieces_of(deg));
+    st.v[slot] = v;
+    st.deg[slot] = deg;
+    st.poff[slot] = po;
+    atomicAdd(&st.degsum, (unsigned long long)deg);
+}
+
+// Block-uniform call (every thread, after a barrier).
+__device__ __forceinline__ void stager_flush(Stager &st, int64_t *q_next, unsigned long long *ctr_next)
+{
+    __syncthreads();
+    const int cnt = st.count;
+    if (cnt == 0) return;
+    if (threadIdx.x == 0) {
+        st.base = (long long)atomicAdd(ctr_next + 0, (unsigned long long)st.pieces);
+        atomicAdd(ctr_next + 1, (unsigned long long)cnt);
+        atomicAdd(ctr_next + 2, st.degsum);
+    }
+    __syncthreads();
+    const long long base = st.base;
+    for (int k = threadIdx.x; k < cnt; k += BLOCK) {
+        const int32_t v = st.v[k];
+        const int pc = pieces_of(st.deg[k]);
+        int64_t *dst = q_next + base + st.poff[k];
+        for (int p = 0; p < pc; p++) dst[p] = ((int64_t)p << 32) | (int64_t)(uint32_t)v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st.count = 0;
+        st.pieces = 0;
+        st.degsum = 0;
+    }
+    __syncthreads();
+}
+
+// Claim v for F_{i+1} (the compare-and-swap on r[v] of Algorithm "Cluster-BFS
+// search from S", here an atomic OR on a membership bitmap: first setter wins).
+__device__ __forceinline__ void claim(Stager &st, uint64_t *bits_next, int32_t v, int32_t deg)
+{
+    const unsigned long long bit = 1ull << (v & 63);
+    const unsigned long long old = atomicOr(reinterpret_cast<unsigned long long *>(bits_next + (v >> 6)), bit);
+    if (!(old & bit)) stager_push(st, v, deg);
+}
+
+// Contribute x (bits of a neighbour's set) to v: OR the bits not yet in
+// Seen_i(v) into nxt(v); claim v if this call added any of them.
+template <int W>
+__device__ __forceinline__ void contribute(Stager &st, uint64_t *nxt, uint64_t *bits_next,
+                                          const int32_t *row_ptr, int32_t v, const uint64_t (&x)[W])
+{
+    uint64_t *p = nxt + (size_t)v * W;
+    uint64_t added = 0;
+#pragma unroll
+    for (int w = 0; w < W; w++)
+        if (x[w]) {
+            const uint64_t old = or64(p + w, x[w]);
+            added |= x[w] & ~old;
+        }
+    if (added) claim(st, bits_next, v, row_ptr[v + 1] - row_ptr[v]);
+}
+
+// Exclusive block scan of one int per thread; *total receives the sum.
+__device__ __forceinline__ int block_exclusive_scan(int x, int *tmp /*[WAVES+1]*/, int *total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(v, d, 64);
+        if (lane >= d) v += y;
+    }
+    if (lane == 63) tmp[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < WAVES; w++) {
+            int t = tmp[w];
+            tmp[w] = acc;
+            acc += t;
+        }
+        tmp[WAVES] = acc;
+    }
+    __syncthreads();
+    *total = tmp[WAVES];
+    const int r = v - x + tmp[wid];
+    __syncthreads();
+    return r;
+}
+
+}  // namespace cbfs

@@ -1,0 +1,314 @@
+// cbfs_run_batch: argument checks, workspace layout, cluster grouping and the
+// host-driven level loop (Algorithm "Cluster-BFS search from S": init, then
+// rounds of vertex phase + edge phase until the frontier is empty).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cbfs.h"
+#include "cbfs_internal.h"
+#include "cbfs_kernels.h"
+
+namespace cbfs {
+
+namespace {
+thread_local std::string g_last_error;
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+}  // namespace
+
+cbfs_status fail(cbfs_status s, const char *msg)
+{
+    g_last_error = msg ? msg : "";
+    return s;
+}
+
+cbfs_status hip_fail(const char *what, int err)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString((hipError_t)err);
+    return CBFS_E_HIP;
+}
+
+// How a batch is laid out: W words per vertex per group, WC words per cluster,
+// clusters packed W/WC per group in batch order.
+struct Plan {
+    int64_t n = 0, m = 0;
+    int32_t C = 0, R = 0;
+    int32_t WC = 1;       // words per cluster (output W)
+    int32_t W = 1;        // words per vertex in a group
+    int32_t per_group = 1;
+    int32_t groups = 0;
+    int32_t slots = 1;
+    int32_t mode = CBFS_MODE_HOST_LOOP;
+    float alpha = 15.0f, beta = 20.0f;
+    int32_t force_pull = 0;
+    int32_t ntiles = 0;
+    int64_t nwords = 0;
+    int64_t qcap = 0;
+    int32_t total_sources = 0;
+    // workspace offsets
+    size_t off_tiles_row = 0, off_tiles_edge = 0, off_cptr = 0, off_src = 0, off_slots = 0, slot_bytes = 0;
+    size_t total = 0;
+};
+
+static bool valid_w(int W, int WC)
+{
+    return (W == 1 && WC == 1) || (W == 3 && WC == 3) || (W == 2 && (WC == 1 || WC == 2)) ||
+           (W == 4 && (WC == 1 || WC == 2 || WC == 4)) || (W == 8 && (WC == 1 || WC == 2 || WC == 4));
+}
+
+static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *t, Plan &p,
+                             bool check_sources)
+{
+    if (!g || !b) return fail(CBFS_E_ARG, "cbfs_run_batch: null graph or batch");
+    if (g->n < 1 || g->n >= INT32_MAX || g->m < 0 || g->m >= INT32_MAX || !g->row_ptr || (g->m > 0 && !g->col))
+        return fail(CBFS_E_ARG, "cbfs_run_batch: bad graph sizes or pointers");
+    if (b->num_clusters < 1 || !b->cluster_ptr || !b->sources)
+        return fail(CBFS_E_ARG, "cbfs_run_batch: empty batch or null cluster arrays");
+    if (b->radius < 0 || b->radius > 1024) return fail(CBFS_E_ARG, "cbfs_run_batch: radius outside [0, 1024]");
+    if (b->cluster_ptr[0] != 0) return fail(CBFS_E_ARG, "cbfs_run_batch: cluster_ptr[0] != 0");
+    int32_t kmax = 0;
+    for (int32_t c = 0; c < b->num_clusters; c++) {
+        int32_t k = b->cluster_ptr[c + 1] - b->cluster_ptr[c];
+        if (k < 1 || k > CBFS_MAX_SOURCES)
+            return fail(CBFS_E_TOO_MANY_SOURCES, "cbfs_run_batch: a cluster has 0 or more than 256 sources");
+        kmax = std::max(kmax, k);
+    }
+    if (check_sources) {
+        std::vector<int32_t> tmp;
+        for (int32_t c = 0; c < b->num_clusters; c++) {
+            const int32_t *S = b->sources + b->cluster_ptr[c];
+            int32_t k = b->cluster_ptr[c + 1] - b->cluster_ptr[c];
+            for (int32_t i = 0; i < k; i++)
+                if (S[i] < 0 || S[i] >= g->n) return fail(CBFS_E_RANGE, "cbfs_run_batch: source outside [0, n)");
+            tmp.assign(S, S + k);
+            std::sort(tmp.begin(), tmp.end());
+            if (std::adjacent_find(tmp.begin(), tmp.end()) != tmp.end())
+                return fail(CBFS_E_DUP_SOURCE, "cbfs_run_batch: a vertex appears twice in one cluster");
+        }
+    }
+    p.n = g->n;
+    p.m = g->m;
+    p.C = b->num_clusters;
+    p.R = b->radius;
+    p.total_sources = b->cluster_ptr[p.C];
+    p.WC = (kmax + 63) / 64;
+    // defaults
+    p.W = p.WC == 3 ? 3 : 4;
+    if (p.W < p.WC) p.W = p.WC;
+    p.mode = CBFS_MODE_HOST_LOOP;
+    if (t) {
+        if (t->mode < 0 || t->mode > CBFS_MODE_PERSISTENT) return fail(CBFS_E_ARG, "cbfs_tuning: bad mode");
+        if (t->mode == CBFS_MODE_PERSISTENT)
+            return fail(CBFS_E_ARG, "cbfs_tuning: persistent mode not available in this build");
+        if (t->mode != CBFS_MODE_AUTO) p.mode = t->mode;
+        if (t->group_words != 0) p.W = t->group_words;
+        if (t->block_size != 0 && t->block_size != BLOCK) return fail(CBFS_E_ARG, "cbfs_tuning: block_size must be 256");
+        if (t->alpha != 0.0f) p.alpha = t->alpha;
+        if (t->beta != 0.0f) p.beta = t->beta;
+        if (t->beta < 0.0f) return fail(CBFS_E_ARG, "cbfs_tuning: beta < 0");
+        p.force_pull = t->force_pull;
+        if (t->concurrent_groups < 0) return fail(CBFS_E_ARG, "cbfs_tuning: concurrent_groups < 0");
+    }
+    if (!valid_w(p.W, p.WC))
+        return fail(CBFS_E_ARG, "cbfs_tuning: group_words must be one of 1,2,4,8 and a multiple of the cluster words");
+    // never pack more words than clusters need
+    p.per_group = p.W / p.WC;
+    while (p.per_group > 1 && p.per_group / 2 >= p.C && valid_w(p.W / 2, p.WC)) {
+        p.W /= 2;
+        p.per_group = p.W / p.WC;
+    }
+    p.groups = (p.C + p.per_group - 1) / p.per_group;
+    p.slots = 1;
+    p.nwords = (p.n + 63) / 64;
+    p.qcap = p.n + p.m / PIECE + 1;
+    p.ntiles = (int32_t)((p.n + p.m + TILE_ITEMS - 1) / TILE_ITEMS);
+    if (p.ntiles < 1) p.ntiles = 1;
+
+    size_t off = 0;
+    p.off_tiles_row = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)(p.ntiles + 1));
+    p.off_tiles_edge = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)(p.ntiles + 1));
+    p.off_cptr = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)(p.C + 1));
+    p.off_src = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)std::max(1, p.total_sources));
+    p.off_slots = off;
+    size_t sb = 0;
+    sb += 3 * align_up(sizeof(uint64_t) * (size_t)p.n * p.W);
+    sb += 2 * align_up(sizeof(int64_t) * (size_t)p.qcap);
+    sb += 3 * align_up(sizeof(uint64_t) * (size_t)p.nwords);
+    sb += align_up(sizeof(unsigned long long) * 12);
+    p.slot_bytes = sb;
+    p.total = off + sb * (size_t)p.slots;
+    return CBFS_OK;
+}
+
+static SlotArgs slot_at(const Plan &p, char *ws, int slot)
+{
+    SlotArgs s{};
+    char *b = ws + p.off_slots + p.slot_bytes * (size_t)slot;
+    size_t words = align_up(sizeof(uint64_t) * (size_t)p.n * p.W);
+    s.A = (uint64_t *)b;
+    b += words;
+    s.B = (uint64_t *)b;
+    b += words;
+    s.seen = (uint64_t *)b;
+    b += words;
+    size_t qb = align_up(sizeof(int64_t) * (size_t)p.qcap);
+    s.q0 = (int64_t *)b;
+    b += qb;
+    s.q1 = (int64_t *)b;
+    b += qb;
+    size_t bb = align_up(sizeof(uint64_t) * (size_t)p.nwords);
+    s.bits0 = (uint64_t *)b;
+    b += bb;
+    s.bits1 = (uint64_t *)b;
+    b += bb;
+    s.bits2 = (uint64_t *)b;
+    b += bb;
+    s.ctr = (unsigned long long *)b;
+    s.nwords = p.nwords;
+    return s;
+}
+
+static GroupDesc group_desc(const Plan &p, const cbfs_batch *b, int32_t grp)
+{
+    GroupDesc d{};
+    d.c0 = grp * p.per_group;
+    d.nc = std::min(p.per_group, p.C - d.c0);
+    for (int j = 0; j < d.nc; j++) {
+        const int32_t k = b->cluster_ptr[d.c0 + j + 1] - b->cluster_ptr[d.c0 + j];
+        for (int x = 0; x < p.WC; x++) {
+            const int lo = 64 * x;
+            uint64_t w = 0;
+            if (k >= lo + 64) w = ~0ull;
+            else if (k > lo) w = (1ull << (k - lo)) - 1;
+            d.full[j * p.WC + x] = w;
+        }
+    }
+    return d;
+}
+
+// Pinned host words the level loop reads the frontier counters into.
+static unsigned long long *pinned_counters()
+{
+    thread_local unsigned long long *buf = nullptr;
+    if (!buf) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, 64, hipHostMallocDefault) != hipSuccess) return nullptr;
+        buf = (unsigned long long *)p;
+    }
+    return buf;
+}
+
+static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_batch *b, uint32_t *dist,
+                                 uint64_t *masks, int32_t *status, char *ws, hipStream_t st)
+{
+    GraphArgs gr{};
+    gr.n = p.n;
+    gr.m = p.m;
+    gr.row_ptr = g->row_ptr;
+    gr.col = g->col;
+    gr.tile_row = (const int32_t *)(ws + p.off_tiles_row);
+    gr.tile_edge = (const int32_t *)(ws + p.off_tiles_edge);
+    gr.ntiles = p.ntiles;
+    const int32_t *d_cptr = (const int32_t *)(ws + p.off_cptr);
+    const int32_t *d_src = (const int32_t *)(ws + p.off_src);
+    OutArgs o{dist, masks, status, p.R};
+    unsigned long long *hc = pinned_counters();
+    if (!hc) return fail(CBFS_E_NOMEM, "cbfs_run_batch: pinned host counters");
+    hipError_t e;
+    if ((e = launch_tiles(g->row_ptr, p.n, p.m, p.ntiles, (int32_t *)(ws + p.off_tiles_row),
+                          (int32_t *)(ws + p.off_tiles_edge), st)) != hipSuccess)
+        return hip_fail("tiles", e);
+    const SlotArgs s = slot_at(p, ws, 0);
+    const int64_t max_rounds = p.n + 2 * (int64_t)p.R + 4;
+    for (int32_t grp = 0; grp < p.groups; grp++) {
+        const GroupDesc gd = group_desc(p, b, grp);
+        if ((e = launch_init(p.W, s, p.n, gd, o, st)) != hipSuccess) return hip_fail("init", e);
+        if ((e = launch_seed(p.W, p.WC, s, gr, gd, d_src, d_cptr, st)) != hipSuccess) return hip_fail("seed", e);
+        bool dense = false;
+        for (int32_t round = 0;; round++) {
+            if (round > max_rounds) return fail(CBFS_E_HIP, "cbfs_run_batch: level loop did not terminate");
+            if ((e = hipMemcpyAsync(hc, s.ctr + 4 * (round % 3), 3 * sizeof(unsigned long long),
+                                    hipMemcpyDeviceToHost, st)) != hipSuccess)
+                return hip_fail("counter copy", e);
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail("level sync", e);
+            const int64_t pieces = (int64_t)hc[0], verts = (int64_t)hc[1], degsum = (int64_t)hc[2];
+            if (verts == 0) break;
+            // direction choice (Appendix A, Algorithm "EdgeMap"): dense when the
+            // frontier plus its out-arcs is a large share of the graph; stay dense
+            // while the frontier is still large.
+            if (p.force_pull) dense = true;
+            else if (p.alpha < 0) dense = false;
+            else if (!dense) dense = (double)(verts + degsum) > (double)p.m / p.alpha;
+            else dense = (double)verts > (double)p.n / p.beta;
+            if (dense) e = launch_pull(p.W, p.WC, s, gr, gd, o, round, pieces, st);
+            else e = launch_push(p.W, p.WC, s, gr, gd, o, round, pieces, st);
+            if (e != hipSuccess) return hip_fail(dense ? "pull" : "push", e);
+        }
+        if ((e = launch_finalize(p.W, p.WC, s, p.n, gd, o, st)) != hipSuccess) return hip_fail("finalize", e);
+    }
+    return CBFS_OK;
+}
+
+}  // namespace cbfs
+
+using namespace cbfs;
+
+extern "C" const char *cbfs_status_string(cbfs_status s)
+{
+    switch (s) {
+    case CBFS_OK: return "CBFS_OK";
+    case CBFS_E_ARG: return "CBFS_E_ARG";
+    case CBFS_E_RANGE: return "CBFS_E_RANGE";
+    case CBFS_E_DUP_SOURCE: return "CBFS_E_DUP_SOURCE";
+    case CBFS_E_TOO_MANY_SOURCES: return "CBFS_E_TOO_MANY_SOURCES";
+    case CBFS_E_RADIUS: return "CBFS_E_RADIUS";
+    case CBFS_E_WORKSPACE: return "CBFS_E_WORKSPACE";
+    case CBFS_E_HIP: return "CBFS_E_HIP";
+    case CBFS_E_NOMEM: return "CBFS_E_NOMEM";
+    default: return "CBFS_E_UNKNOWN";
+    }
+}
+
+extern "C" const char *cbfs_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" size_t cbfs_run_batch_workspace_size(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *t)
+{
+    Plan p;
+    if (make_plan(g, b, t, p, false) != CBFS_OK) return 0;
+    return p.total;
+}
+
+extern "C" cbfs_status cbfs_run_batch(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *t,
+                                      uint32_t *dist, uint64_t *masks, int32_t *cluster_status,
+                                      void *workspace, size_t workspace_bytes, void *stream)
+{
+    g_last_error.clear();
+    Plan p;
+    cbfs_status rc = make_plan(g, b, t, p, true);
+    if (rc != CBFS_OK) return rc;
+    if (!dist || !masks || !cluster_status || !workspace)
+        return fail(CBFS_E_ARG, "cbfs_run_batch: null output or workspace");
+    if (workspace_bytes < p.total) return fail(CBFS_E_WORKSPACE, "cbfs_run_batch: workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ws + p.off_cptr, b->cluster_ptr, sizeof(int32_t) * (size_t)(p.C + 1),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_fail("cluster_ptr upload", e);
+    if ((e = hipMemcpyAsync(ws + p.off_src, b->sources, sizeof(int32_t) * (size_t)p.total_sources,
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_fail("sources upload", e);
+    // the host arrays belong to the caller once we return
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail("upload sync", e);
+    return run_host_loop(p, g, b, dist, masks, cluster_status, ws, st);
+}

@@ -1,0 +1,163 @@
+"""GPU parity: the HIP Cluster-BFS against the CPU oracle, bit for bit.
+
+Each case generates a raw graph with the seeded generators, cleans it and
+selects clusters on both sides independently (library entry points vs oracle
+code), checks that the inputs agree, then compares every output word: dist,
+all offset planes and the per-cluster status (integer work: exact equality).
+Tuning knobs (direction, group width) must never change a bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def prepare(n, s, d, centers_fn, k, hops):
+    """Both sides clean and select on their own; they must agree."""
+    import paper_2410_17226_amd as P
+    rp, col, o2n = P.build_csr(n, s, d)
+    orp, ocol, oo2n = oracle.clean_csr(n, s, d)
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+    centers = centers_fn(rp)
+    cp, src = P.select_clusters(rp, col, centers, k, hops)
+    ocp, osrc = oracle.build_clusters(orp, ocol, centers, k, hops)
+    assert np.array_equal(cp, ocp) and np.array_equal(src, osrc)
+    return (rp, col, cp, src), (orp, ocol, ocp, osrc)
+
+
+def gpu_cbfs(rp, col, cp, src, R, tuning=None):
+    torch = _torch()
+    import paper_2410_17226_amd as P
+    print(f"[gpu_cbfs] n={rp.size - 1} m={col.size} C={cp.size - 1} R={R} tuning={tuning}", flush=True)
+    rp_d = torch.from_numpy(rp).cuda()
+    col_d = torch.from_numpy(col if col.size else np.zeros(1, np.int32)).cuda()
+    if col.size == 0:
+        col_d = col_d[:0]
+    dist, masks, st = P.run_batch(rp_d, col_d, cp, src, R, tuning)
+    torch.cuda.synchronize()
+    return (dist.cpu().numpy().view(np.uint32), masks.cpu().numpy().view(np.uint64), st.cpu().numpy())
+
+
+def assert_same(gpu, ref, where=""):
+    gd, gm, gs = gpu
+    od, om, os_ = ref
+    assert np.array_equal(gs, os_), f"{where} status {gs} vs {os_}"
+    ok = os_ == 0
+    assert np.array_equal(gd[ok], od[ok]), f"{where} dist mismatch in clusters {np.nonzero(ok)[0]}"
+    for c in np.nonzero(ok)[0]:
+        if not np.array_equal(gm[c], om[c]):
+            bad = np.argwhere(gm[c] != om[c])
+            raise AssertionError(f"{where} masks of cluster {c} differ at {bad[:5].tolist()}")
+
+
+TUNINGS = [None, dict(alpha=-1.0), dict(force_pull=1), dict(group_words=1), dict(group_words=8, alpha=5.0)]
+
+
+def tuning_of(t, WC=1):
+    import paper_2410_17226_amd as P
+    if t is None:
+        return None
+    t = dict(t)
+    if "group_words" in t and t["group_words"] % WC:
+        t["group_words"] = WC
+    return P.Tuning(**t)
+
+
+def small_cases():
+    cases = []
+    for seed in range(3):
+        cases.append(("gnp", lambda seed=seed: synth.random_graph(120, 0.05, seed), 1, 64))
+        cases.append(("tree", lambda seed=seed: synth.random_tree(150, seed), 1, 64))
+    cases.append(("grid_r2", lambda: synth.grid_edges(30, 0.1, seed=1), 2, 64))
+    cases.append(("rmat10", lambda: synth.rmat_edges(10, 16, seed=5), 1, 64))
+    cases.append(("rmat10_k150", lambda: synth.rmat_edges(10, 16, seed=6), 1, 150))
+    cases.append(("rmat11_k256", lambda: synth.rmat_edges(11, 16, seed=7), 1, 256))
+    cases.append(("rmat10_r3", lambda: synth.rmat_edges(10, 4, seed=8), 3, 64))
+    return cases
+
+
+@pytest.mark.parametrize("name,gen,R,k", small_cases(), ids=[c[0] for c in small_cases()])
+@pytest.mark.parametrize("tun", TUNINGS, ids=["default", "push", "pull", "w1", "w8"])
+def test_parity_small(name, gen, R, k, tun):
+    n, s, d = gen()
+    hops = R
+    ncent = 9
+    ours, ref_in = prepare(n, s, d, lambda rp: np.concatenate(
+        [oracle.top_degree(rp, 5), synth.random_centers(rp.size - 1, 4, 3)]).astype(np.int32)
+        if rp.size - 1 >= ncent else np.arange(rp.size - 1, dtype=np.int32), k, hops)
+    rp, col, cp, src = ours
+    WC = (int(np.diff(cp).max()) + 63) // 64
+    gpu = gpu_cbfs(rp, col, cp, src, R, tuning_of(tun, WC))
+    ref = oracle.cbfs(*ref_in, R=R)
+    assert_same(gpu, ref, name)
+
+
+def test_parity_hand_fixture(golden_dir):
+    from test_oracle import read_fixture
+    fx = read_fixture(golden_dir)
+    e = np.array(fx["edges"], np.int64)
+    import paper_2410_17226_amd as P
+    rp, col, _ = P.build_csr(fx["n"], e[:, 0], e[:, 1])
+    S = np.array(fx["sources"], np.int32)
+    gd, gm, gs = gpu_cbfs(rp, col, np.array([0, S.size], np.int32), S, fx["R"])
+    assert gs[0] == 0
+    for v, dv, m1, m0, p1 in fx["vertex"]:
+        assert gd[0, v] == dv
+        assert [int(x) for x in gm[0, :, v, 0]] == [m1, m0, p1]
+
+
+def test_parity_disconnected_and_violations():
+    # a graph kept whole (no LCC): two components plus isolated vertices
+    n, s, d = synth.random_graph(200, 0.012, 11)
+    import paper_2410_17226_amd as P
+    rp, col, _ = P.build_csr(n, s, d, flags=7)
+    orp, ocol, _ = oracle.clean_csr(n, s, d, flags=7)
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+    deg = np.diff(rp)
+    centers = np.nonzero(deg > 0)[0][:12].astype(np.int32)
+    cp, src = P.select_clusters(rp, col, centers, 64, 2)   # radius-2 clusters ...
+    for R in (1, 2):                                        # ... violate R = 1
+        for tun in (None, dict(force_pull=1), dict(alpha=-1.0)):
+            gpu = gpu_cbfs(rp, col, cp, src, R, tuning_of(tun))
+            ref = oracle.cbfs(orp, ocol, cp, src, R=R)
+            assert_same(gpu, ref, f"R={R} {tun}")
+            if R == 1:
+                assert (ref[2] != 0).any()
+    # an isolated vertex as a single-source cluster
+    iso = np.nonzero(deg == 0)[0]
+    if iso.size:
+        cp1 = np.array([0, 1], np.int32)
+        src1 = iso[:1].astype(np.int32)
+        assert_same(gpu_cbfs(rp, col, cp1, src1, 1), oracle.cbfs(orp, ocol, cp1, src1, R=1), "isolated")
+
+
+def workload_inputs(name):
+    cfg = configs.WORKLOADS[name]
+    n, s, d = configs.raw_graph(name)
+
+    def centers_fn(rp):
+        if cfg["centers"] == "top_degree":
+            return oracle.top_degree(rp, cfg["count"])
+        return synth.random_centers(rp.size - 1, cfg["count"], cfg["seed"]).astype(np.int32)
+    return cfg, prepare(n, s, d, centers_fn, cfg["k"], cfg["hops"])
+
+
+@pytest.mark.parametrize("name", ["rmat12_small", "rmat16_batch", "grid128_small", "chunglu16_small", "rmat14"])
+def test_parity_workloads_small(name):
+    cfg, (ours, ref_in) = workload_inputs(name)
+    rp, col, cp, src = ours
+    gpu = gpu_cbfs(rp, col, cp, src, cfg["R"])
+    ref = oracle.cbfs(*ref_in, R=cfg["R"])
+    assert_same(gpu, ref, name)
+    assert (ref[2] == 0).all()
