@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched Cluster-BFS hot path on one MI355X.
+
+Workload: the seeded R-MAT graph of scale 22, edge factor 16, quadrant
+probabilities (0.57, 0.19, 0.19, 0.05), symmetrized, deduplicated, self-loops
+removed, largest component kept (~2.39M vertices, ~128.3M arcs, int32 CSR);
+256 radius-1 clusters whose centers are the 256 highest-degree vertices (ties
+by id), each center plus its 63 lowest-id neighbours.  Synthetic stand-in for
+the paper's real social/web graphs.
+
+One step = one cbfs_run_batch over all 256 clusters (every output written),
+with the graph, outputs and workspace already resident in device memory.
+Reported: source-GTEPS = sum_c k_c * m / step time; the roofline of the
+dominant kernel; the plain form (one cluster per call, same kernels); the CPU
+oracle on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "source-GTEPS (sources×edges/s) + %HBM roofline; batched vs plain; query p50/p99"
+KERNEL_SOURCES = ["cbfs_device.h", "cbfs_round.h", "cbfs_kernels.hip", "cbfs_kernels.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2410_17226_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(n, m, stats, C, k_w, R):
+    """Compulsory HBM bytes of one batch (the per-group model of the design):
+    per frontier appearance of a vertex its row-pointer pair (8 B), its arcs
+    (4 B each), and its own state words read/written (24 B per word); the
+    outputs written once (dist 4 B + 2R+1 planes of k_w words per cluster and
+    vertex); and the per-group state clear (16 B per word and vertex)."""
+    W = stats["group_words"]
+    fv, fa = stats["frontier_vertices"], stats["frontier_arcs"]
+    traversal = 8 * fv + 4 * fa
+    own_state = 24 * W * fv
+    outputs = C * n * (4 + 8 * k_w * (2 * R + 1))
+    init = stats["groups"] * n * 16 * W
+    return traversal + own_state + outputs + init
+
+
+def load_traffic(kind: str):
+    """Measured HBM bytes per launch from committed rocprofv3 counter runs,
+    only if they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kind}_rmat22_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", type=int, default=0, help="0 auto, 1 host loop, 2 persistent")
+    ap.add_argument("--group-words", type=int, default=0)
+    ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-clusters", type=int, default=2, help="clusters in the CPU oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the batch of clusters shards "
+                                   "across GPUs without communication (see DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2410_17226_amd as P
+    import synth
+    from synth import configs
+
+    cfg = configs.WORKLOADS["rmat22"]
+    t0 = time.time()
+    a, b, c = cfg["abc"]
+    n_in, src, dst = synth.rmat_edges(cfg["scale"], cfg["edge_factor"], a, b, c, seed=cfg["seed"])
+    rp, col, _ = P.build_csr(n_in, src, dst)
+    del src, dst
+    n, m = rp.size - 1, col.size
+    centers = P.top_degree(rp, cfg["count"])
+    cptr, sources = P.select_clusters(rp, col, centers, cfg["k"], cfg["hops"])
+    R = cfg["R"]
+    C = cptr.size - 1
+    ksum = int(cptr[-1])
+    k_w = (int(np.diff(cptr).max()) + 63) // 64
+    setup_s = time.time() - t0
+    print(f"[bench] graph n={n} m={m} clusters={C} sources={ksum} setup {setup_s:.1f}s", file=sys.stderr,
+          flush=True)
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    rp_d = torch.from_numpy(rp).to(dev)
+    col_d = torch.from_numpy(col).to(dev)
+    tuning = P.Tuning(mode=args.mode, group_words=args.group_words, concurrent_groups=args.slots)
+    dist = torch.empty((C, n), dtype=torch.int32, device=dev)
+    masks = torch.empty((C, 2 * R + 1, n, k_w), dtype=torch.int64, device=dev)
+    status = torch.empty(C, dtype=torch.int32, device=dev)
+    ws_bytes = P.run_batch_workspace_size(rp_d, col_d, cptr, sources, R, tuning)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    out = (dist, masks, status)
+
+    for _ in range(args.warmup):
+        P.run_batch(rp_d, col_d, cptr, sources, R, tuning, out=out, workspace=ws)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    P.profile_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.time()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        P.run_batch(rp_d, col_d, cptr, sources, R, tuning, out=out, workspace=ws, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - wall0
+    prof = P.profile_read()
+    P.profile_enable(False)
+    stats = P.last_run_stats()
+    step_ms = ev0.elapsed_time(ev1) / args.steps
+    assert (status.cpu().numpy() == 0).all(), "a cluster reported a radius violation"
+    gteps = ksum * m / (step_ms * 1e-3) / 1e9
+    print(f"[bench] batched: {step_ms:.2f} ms/step ({wall / args.steps * 1e3:.2f} wall) GTEPS={gteps:.1f} "
+          f"stats={stats} prof={prof}", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel
+    kind, (launches, total_ms) = max(prof.items(), key=lambda kv: kv[1][1])
+    avg_ms = total_ms / max(1, launches)
+    B_alg_step = algorithmic_bytes(n, m, stats, C, k_w, R)
+    if kind == "persistent":
+        per_launch = B_alg_step * args.steps / launches
+        unit_note = "one batch (all groups) per launch"
+    elif kind == "pull":
+        W = stats["group_words"]
+        per_launch = 4 * m + 4 * (n + 1) + n // 8 + 8 * W * n
+        unit_note = "one dense pass over the CSR and the group state per launch"
+    else:
+        per_launch = B_alg_step * args.steps / launches
+        unit_note = "batch bytes spread over the launches"
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = load_traffic(kind)
+    roofline = {"bound": "hbm", "kernel": kind, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "bytes_per_launch": int(per_launch), "avg_launch_ms": round(avg_ms, 3), "launches": launches,
+                "units": unit_note, "step_algorithmic_bytes": int(B_alg_step),
+                "step_frac": round(B_alg_step / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    # plain form: one cluster per call, same kernels and defaults
+    plain = None
+    if not args.no_plain:
+        one = (dist[:1], masks[:1], status[:1])
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for ci in range(C):
+            cp1 = np.array([0, cptr[ci + 1] - cptr[ci]], np.int32)
+            P.run_batch(rp_d, col_d, cp1, sources[cptr[ci]:cptr[ci + 1]], R, tuning, out=one, workspace=ws,
+                        stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = ev0.elapsed_time(ev1)
+        plain = {"value": round(ksum * m / (plain_ms * 1e-3) / 1e9, 2), "ms": round(plain_ms, 2),
+                 "calls": C, "batched_speedup": round(plain_ms / step_ms, 2)}
+        print(f"[bench] plain: {plain}", file=sys.stderr, flush=True)
+
+    # CPU oracle on a bounded sample (the first clusters), also checked against the GPU
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        nc = args.cpu_clusters
+        cps = cptr[: nc + 1]
+        srcs = sources[: cps[-1]]
+        P.run_batch(rp_d, col_d, cptr, sources, R, tuning, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t = time.time()
+        od, om, ost = oracle.cbfs(rp, col, cps, srcs, R=R, nthreads=threads)
+        cpu_s = time.time() - t
+        same = bool(np.array_equal(dist[:nc].cpu().numpy().view(np.uint32), od) and
+                    np.array_equal(masks[:nc].cpu().numpy().view(np.uint64), om))
+        cpu = {"value": round(int(cps[-1]) * m / cpu_s / 1e9, 3), "unit": "GTEPS", "cores": threads,
+               "kind": "oracle", "sample": f"first {nc} clusters ({int(cps[-1])} sources, one BFS each) "
+                                           f"of the same workload, {cpu_s:.1f} s",
+               "gpu_matches_sample": same}
+        print(f"[bench] cpu: {cpu}", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC, "value": round(gteps, 2), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "rmat22_batch256", "graph": "R-MAT scale 22 ef 16 (0.57,0.19,0.19,0.05)",
+                   "n": n, "m_arcs": m, "clusters": C, "sources_per_cluster": int(cfg["k"]), "radius": R,
+                   "group_words": stats["group_words"], "mode": stats["mode"], "slots": stats["slots"],
+                   "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "plain": plain,
+        "run_stats": stats,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -154,7 +154,8 @@ typedef struct {
 } cbfs_batch;
 
 enum {
-    CBFS_MODE_AUTO = 0,       /* library's choice                                          */
+    CBFS_MODE_AUTO = 0,       /* library's choice: host loop on graphs with average degree
+                                 >= 8, persistent below (many rounds, small frontiers)     */
     CBFS_MODE_HOST_LOOP = 1,  /* one launch per round, frontier size read back each round  */
     CBFS_MODE_PERSISTENT = 2  /* one cooperative launch for the whole batch, device-side
                                  level loop with grid barriers, no host round trips         */
@@ -171,6 +172,10 @@ typedef struct {
                                   < 0 forces push every round                           */
     float beta;                /* stay pull while |F| > n / beta; 0 = auto              */
     int32_t force_pull;        /* 1: pull every round (testing)                         */
+    int32_t blocks_per_cu;     /* persistent mode: resident blocks per compute unit;
+                                  0 = as many as fit                                    */
+    int32_t schedule;          /* persistent mode: 0 = blocks take work items from a
+                                  shared counter, 1 = fixed stride over the items       */
     int32_t reserved;
 } cbfs_tuning;
 
@@ -190,6 +195,54 @@ size_t cbfs_run_batch_workspace_size(const cbfs_csr *g, const cbfs_batch *b, con
 cbfs_status cbfs_run_batch(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *t,
                            uint32_t *dist, uint64_t *masks, int32_t *cluster_status,
                            void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ *
+ * Diagnostics (host).
+ *
+ * cbfs_last_run_stats: counts of the calling thread's last cbfs_run_batch,
+ * waiting for it to finish.  frontier_vertices is the sum over groups and
+ * rounds of |F_i|, frontier_arcs the sum of the out-degrees of those
+ * frontiers (how many arcs a frontier-only traversal touches).  device_error:
+ * 0, or 1 (persistent grid barrier timed out) / 2 (round limit hit), in which
+ * case the call returns CBFS_E_HIP and the outputs are unspecified.
+ *
+ * cbfs_profile_enable(1) starts timing every kernel launch the calling thread
+ * makes through this library (HIP events recorded on the call's stream around
+ * each launch; previous records are dropped); cbfs_profile_enable(0) stops.
+ * cbfs_profile_read waits for the recorded launches and returns, per kernel
+ * kind, the launch count and the summed milliseconds (arrays of
+ * CBFS_KERNEL_KINDS entries, host).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t groups;            /* cluster groups searched                     */
+    int64_t group_words;       /* words per vertex of each group              */
+    int64_t slots;             /* groups searched side by side                */
+    int64_t mode;              /* CBFS_MODE_HOST_LOOP or CBFS_MODE_PERSISTENT */
+    int64_t rounds;            /* level-loop rounds, summed over groups       */
+    int64_t push_rounds;
+    int64_t pull_rounds;
+    int64_t frontier_vertices; /* sum of |F_i|                                */
+    int64_t frontier_arcs;     /* sum of deg over F_i                         */
+    int64_t device_error;
+    int64_t persistent_blocks; /* grid of the persistent launch (0 in host-loop mode) */
+} cbfs_run_stats;
+
+cbfs_status cbfs_last_run_stats(cbfs_run_stats *out);
+
+enum {
+    CBFS_KERNEL_TILES = 0,
+    CBFS_KERNEL_INIT = 1,
+    CBFS_KERNEL_SEED = 2,
+    CBFS_KERNEL_PUSH = 3,
+    CBFS_KERNEL_PULL = 4,
+    CBFS_KERNEL_FINALIZE = 5,
+    CBFS_KERNEL_PERSISTENT = 6,
+    CBFS_KERNEL_LABELS = 7,
+    CBFS_KERNEL_QUERY = 8,
+    CBFS_KERNEL_KINDS = 9
+};
+cbfs_status cbfs_profile_enable(int32_t enable);
+cbfs_status cbfs_profile_read(int64_t *launches, double *total_ms);
 
 /* ------------------------------------------------------------------------ *
  * Landmark-labeling queries over cluster labels (Section 4.2; Algorithm

@@ -39,10 +39,10 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C + OpenMP)."""
+    """Compile the oracle with gcc (plain C + pthreads)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-pthread", "-fPIC", "-shared",
                                "-Wall", "-Wextra", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
@@ -97,6 +97,9 @@ def bfs(row_ptr, col, src: int) -> np.ndarray:
 def _clusters(cluster_ptr, sources):
     cluster_ptr = np.ascontiguousarray(cluster_ptr, dtype=np.int32)
     sources = np.ascontiguousarray(sources, dtype=np.int32)
+    if cluster_ptr.size < 1 or cluster_ptr[0] != 0 or np.any(np.diff(cluster_ptr) < 0) \
+            or cluster_ptr[-1] != sources.size:
+        raise ValueError("cluster_ptr must start at 0, not decrease, and end at len(sources)")
     return cluster_ptr, sources, cluster_ptr.size - 1
 
 

@@ -38,12 +38,11 @@
  * non-empty intersection (Section 4.2, answering queries with clustered
  * landmarks), and a BFS-certificate checker for any encoded output.
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
-#ifdef _OPENMP
-#include <omp.h>
-#endif
+#include <unistd.h>
 
 #define OR_OK 0
 #define OR_E_ARG (-1)
@@ -51,14 +50,79 @@
 #define OR_E_NOMEM (-8)
 #define UNREACHED (-1)
 
+#define MAX_THREADS 256
+
+/* Threads to use: the request, else OMP_NUM_THREADS, else the online CPUs. */
 static int nthreads_or_default(int32_t nthreads)
 {
-#ifdef _OPENMP
-    if (nthreads <= 0) nthreads = omp_get_max_threads();
-#else
-    nthreads = 1;
-#endif
-    return nthreads < 1 ? 1 : nthreads;
+    if (nthreads <= 0) {
+        const char *env = getenv("OMP_NUM_THREADS");
+        nthreads = env ? atoi(env) : 0;
+        if (nthreads <= 0) nthreads = (int32_t)sysconf(_SC_NPROCESSORS_ONLN);
+    }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > MAX_THREADS) nthreads = MAX_THREADS;
+    return nthreads;
+}
+
+/* A plain pthread parallel-for: fn(lo, hi, tid, ctx) over chunks of `grain`
+ * indices of [0, n), handed out in order to nt threads (tid in [0, nt)). */
+typedef void (*range_fn)(int64_t lo, int64_t hi, int tid, void *ctx);
+typedef struct {
+    int64_t n, grain, next;
+    pthread_mutex_t mu;
+    range_fn fn;
+    void *ctx;
+} pfor_job;
+typedef struct {
+    pfor_job *job;
+    int tid;
+} pfor_arg;
+
+static void *pfor_worker(void *p)
+{
+    pfor_arg *a = (pfor_arg *)p;
+    pfor_job *j = a->job;
+    for (;;) {
+        pthread_mutex_lock(&j->mu);
+        const int64_t lo = j->next;
+        const int64_t hi = lo + j->grain < j->n ? lo + j->grain : j->n;
+        j->next = hi;
+        pthread_mutex_unlock(&j->mu);
+        if (lo >= j->n) break;
+        j->fn(lo, hi, a->tid, j->ctx);
+    }
+    return NULL;
+}
+
+static void parallel_for(int64_t n, int64_t grain, int nt, range_fn fn, void *ctx)
+{
+    if (grain < 1) grain = 1;
+    if (nt <= 1 || n <= grain) {
+        if (n > 0) fn(0, n, 0, ctx);
+        return;
+    }
+    pfor_job job;
+    job.n = n;
+    job.grain = grain;
+    job.next = 0;
+    job.fn = fn;
+    job.ctx = ctx;
+    pthread_mutex_init(&job.mu, NULL);
+    pthread_t th[MAX_THREADS];
+    pfor_arg args[MAX_THREADS];
+    int started = 1;
+    for (int t = 0; t < nt; t++) {
+        args[t].job = &job;
+        args[t].tid = t;
+    }
+    for (int t = 1; t < nt; t++) {
+        if (pthread_create(&th[t], NULL, pfor_worker, &args[t]) != 0) break;
+        started++;
+    }
+    pfor_worker(&args[0]);
+    for (int t = 1; t < started; t++) pthread_join(th[t], NULL);
+    pthread_mutex_destroy(&job.mu);
 }
 
 /* Plain FIFO BFS from src.  dist[v] = hops from src, -1 when unreachable.
@@ -94,24 +158,70 @@ int oracle_bfs(int64_t n, const int32_t *row_ptr, const int32_t *col, int32_t sr
 
 /* Distances from a batch of sources, one BFS per source, in parallel over sources.
  * d[j*n + v] = delta(src[j], v). */
+typedef struct {
+    int64_t n;
+    const int32_t *row_ptr, *col, *src;
+    int32_t *d, *queues;
+} bfs_batch_ctx;
+
+static void bfs_batch_body(int64_t lo, int64_t hi, int tid, void *p)
+{
+    bfs_batch_ctx *c = (bfs_batch_ctx *)p;
+    for (int64_t j = lo; j < hi; j++)
+        bfs(c->n, c->row_ptr, c->col, c->src[j], c->d + (size_t)j * (size_t)c->n,
+            c->queues + (size_t)tid * (size_t)c->n);
+}
+
 static int bfs_batch(int64_t n, const int32_t *row_ptr, const int32_t *col,
                      const int32_t *src, int32_t count, int32_t *d, int nthreads)
 {
-    int failed = 0;
-#pragma omp parallel num_threads(nthreads)
-    {
-        int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-        if (!queue) {
-#pragma omp atomic write
-            failed = 1;
+    int nt = nthreads < count ? nthreads : count;
+    if (nt < 1) nt = 1;
+    int32_t *queues = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * (size_t)nt);
+    if (!queues) return OR_E_NOMEM;
+    bfs_batch_ctx c = {n, row_ptr, col, src, d, queues};
+    parallel_for(count, 1, nt, bfs_batch_body, &c);
+    free(queues);
+    return OR_OK;
+}
+
+/* Encode sources i0 .. i0+cnt-1 at every vertex: bit i goes to the plane of
+ * its offset delta_i(v) - delta_0(v); offsets beyond [-R, R], and sources
+ * reaching a vertex the center does not (or the reverse), flag a violation. */
+typedef struct {
+    int64_t n;
+    const int32_t *d0, *db;
+    int32_t cnt, i0, R, W;
+    uint64_t *mc;
+    int violated;
+} encode_ctx;
+
+static void encode_body(int64_t lo, int64_t hi, int tid, void *p)
+{
+    (void)tid;
+    encode_ctx *e = (encode_ctx *)p;
+    const int64_t n = e->n;
+    const int32_t R = e->R, W = e->W;
+    int bad = 0;
+    for (int64_t v = lo; v < hi; v++) {
+        for (int32_t j = 0; j < e->cnt; j++) {
+            const int32_t i = e->i0 + j;
+            const int32_t di = e->db[(size_t)j * (size_t)n + (size_t)v];
+            const int32_t dc = e->d0[v];
+            if (dc == UNREACHED || di == UNREACHED) {
+                if (dc != di) bad = 1;
+                continue;
+            }
+            const int32_t off = di - dc;
+            if (off < -R || off > R) {
+                bad = 1;
+                continue;
+            }
+            e->mc[((size_t)(off + R) * (size_t)n + (size_t)v) * (size_t)W + (size_t)(i / 64)] |=
+                (uint64_t)1 << (i % 64);
         }
-#pragma omp for schedule(dynamic, 1)
-        for (int32_t j = 0; j < count; j++) {
-            if (queue) bfs(n, row_ptr, col, src[j], d + (size_t)j * (size_t)n, queue);
-        }
-        free(queue);
     }
-    return failed ? OR_E_NOMEM : OR_OK;
+    if (bad) __atomic_store_n(&e->violated, 1, __ATOMIC_RELAXED);
 }
 
 int oracle_cbfs(int64_t n, const int32_t *row_ptr, const int32_t *col,
@@ -150,39 +260,38 @@ int oracle_cbfs(int64_t n, const int32_t *row_ptr, const int32_t *col,
             int32_t cnt = k - i0 < batch ? k - i0 : batch;
             rc = bfs_batch(n, row_ptr, col, S + i0, cnt, db, nt);
             if (rc != OR_OK) break;
-#pragma omp parallel for num_threads(nt) schedule(static)
-            for (int64_t v = 0; v < n; v++) {
-                for (int32_t j = 0; j < cnt; j++) {
-                    const int32_t i = i0 + j;
-                    const int32_t di = db[(size_t)j * (size_t)n + (size_t)v];
-                    if (d0[v] == UNREACHED) {
-                        if (di != UNREACHED) {
-#pragma omp atomic write
-                            violated = 1;
-                        }
-                        continue;
-                    }
-                    if (di == UNREACHED) {
-#pragma omp atomic write
-                        violated = 1;
-                        continue;
-                    }
-                    const int32_t off = di - d0[v];
-                    if (off < -R || off > R) {
-#pragma omp atomic write
-                        violated = 1;
-                        continue;
-                    }
-                    mc[((size_t)(off + R) * (size_t)n + (size_t)v) * (size_t)W + (size_t)(i / 64)] |=
-                        (uint64_t)1 << (i % 64);
-                }
-            }
+            encode_ctx ec = {n, d0, db, cnt, i0, R, W, mc, 0};
+            parallel_for(n, 4096, nt, encode_body, &ec);
+            if (ec.violated) violated = 1;
         }
         status[c] = violated ? OR_E_RADIUS : OR_OK;
     }
     free(d0);
     free(db);
     return rc;
+}
+
+typedef struct {
+    int64_t n;
+    const int32_t *db;
+    int32_t cnt;
+    const int32_t *qs, *qt;
+    uint32_t *ans;
+} query_ctx;
+
+static void query_body(int64_t lo, int64_t hi, int tid, void *p)
+{
+    (void)tid;
+    query_ctx *c = (query_ctx *)p;
+    for (int32_t j = 0; j < c->cnt; j++) {
+        const int32_t *d = c->db + (size_t)j * (size_t)c->n;
+        for (int64_t k = lo; k < hi; k++) {
+            const int32_t a = d[c->qs[k]], b = d[c->qt[k]];
+            if (a == UNREACHED || b == UNREACHED) continue;
+            const uint32_t val = (uint32_t)(a + b);
+            if (val < c->ans[k]) c->ans[k] = val;
+        }
+    }
 }
 
 /* Landmark-labeling query by brute force: for each pair (s, t),
@@ -207,16 +316,8 @@ int oracle_query_landmarks(int64_t n, const int32_t *row_ptr, const int32_t *col
         int32_t cnt = total - x0 < nt ? total - x0 : nt;
         rc = bfs_batch(n, row_ptr, col, sources + x0, cnt, db, nt);
         if (rc != OR_OK) break;
-        for (int32_t j = 0; j < cnt; j++) {
-            const int32_t *d = db + (size_t)j * (size_t)n;
-#pragma omp parallel for num_threads(nt) schedule(static)
-            for (int64_t p = 0; p < q; p++) {
-                int32_t a = d[qs[p]], b = d[qt[p]];
-                if (a == UNREACHED || b == UNREACHED) continue;
-                uint32_t val = (uint32_t)(a + b);
-                if (val < ans[p]) ans[p] = val;
-            }
-        }
+        query_ctx qc = {n, db, cnt, qs, qt, ans};
+        parallel_for(q, 4096, nt, query_body, &qc);
     }
     free(db);
     return rc;
@@ -266,50 +367,62 @@ int oracle_query_labels(int64_t n, int32_t num_clusters, int32_t R, const uint32
  * neither); every reached v != s_i has a neighbour at delta_i(v) - 1.  Each
  * reached v must carry bit i in exactly one plane; unreached v carry no bits.
  * Returns the number of violations found (0 = certified), or a negative error. */
-int64_t oracle_certificate(int64_t n, const int32_t *row_ptr, const int32_t *col, int32_t k,
-                           const int32_t *S, int32_t R, int32_t W, const uint32_t *dist,
-                           const uint64_t *masks, int32_t nthreads)
+typedef struct {
+    int64_t n;
+    const int32_t *row_ptr, *col;
+    int32_t k;
+    const int32_t *S;
+    int32_t R, W;
+    int64_t P;
+    const uint32_t *dist;
+    const uint64_t *masks;
+    int32_t *d;
+    int64_t *bad;
+} cert_ctx;
+
+static void cert_decode_body(int64_t lo, int64_t hi, int tid, void *p)
 {
-    if (n <= 0 || k < 1 || k > 64 * W || R < 0) return OR_E_ARG;
-    int nt = nthreads_or_default(nthreads);
-    const int64_t P = 2 * (int64_t)R + 1;
-    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * (size_t)k);
-    if (!d) return OR_E_NOMEM;
+    cert_ctx *c = (cert_ctx *)p;
+    const int64_t n = c->n;
     int64_t bad = 0;
-    /* decode */
-#pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : bad)
-    for (int64_t v = 0; v < n; v++) {
-        for (int32_t i = 0; i < k; i++) {
+    for (int64_t v = lo; v < hi; v++) {
+        for (int32_t i = 0; i < c->k; i++) {
             int32_t found = 0, off = 0;
-            for (int64_t p = 0; p < P; p++) {
-                uint64_t w = masks[((size_t)p * n + v) * W + (size_t)(i / 64)];
+            for (int64_t pl = 0; pl < c->P; pl++) {
+                const uint64_t w = c->masks[((size_t)pl * n + v) * c->W + (size_t)(i / 64)];
                 if ((w >> (i % 64)) & 1) {
                     found++;
-                    off = (int32_t)(p - R);
+                    off = (int32_t)(pl - c->R);
                 }
             }
-            if (dist[v] == UINT32_MAX) {
+            if (c->dist[v] == UINT32_MAX) {
                 if (found) bad++;
-                d[(size_t)i * n + v] = UNREACHED;
+                c->d[(size_t)i * n + v] = UNREACHED;
             } else {
                 if (found != 1) bad++;
-                d[(size_t)i * n + v] = (int32_t)dist[v] + off;
+                c->d[(size_t)i * n + v] = (int32_t)c->dist[v] + off;
             }
         }
     }
-    /* check */
-#pragma omp parallel for num_threads(nt) schedule(dynamic, 1024) reduction(+ : bad)
-    for (int64_t v = 0; v < n; v++) {
-        for (int32_t i = 0; i < k; i++) {
-            const int32_t dv = d[(size_t)i * n + v];
-            if (v == S[i]) {
+    c->bad[tid] += bad;
+}
+
+static void cert_check_body(int64_t lo, int64_t hi, int tid, void *p)
+{
+    cert_ctx *c = (cert_ctx *)p;
+    const int64_t n = c->n;
+    int64_t bad = 0;
+    for (int64_t v = lo; v < hi; v++) {
+        for (int32_t i = 0; i < c->k; i++) {
+            const int32_t dv = c->d[(size_t)i * n + v];
+            if (v == c->S[i]) {
                 if (dv != 0) bad++;
             } else if (dv == 0) {
                 bad++;
             }
             int has_parent = 0;
-            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
-                const int32_t du = d[(size_t)i * n + col[e]];
+            for (int32_t e = c->row_ptr[v]; e < c->row_ptr[v + 1]; e++) {
+                const int32_t du = c->d[(size_t)i * n + c->col[e]];
                 if ((du == UNREACHED) != (dv == UNREACHED)) {
                     bad++;
                     continue;
@@ -321,6 +434,24 @@ int64_t oracle_certificate(int64_t n, const int32_t *row_ptr, const int32_t *col
             if (dv > 0 && !has_parent) bad++;
         }
     }
+    c->bad[tid] += bad;
+}
+
+int64_t oracle_certificate(int64_t n, const int32_t *row_ptr, const int32_t *col, int32_t k,
+                           const int32_t *S, int32_t R, int32_t W, const uint32_t *dist,
+                           const uint64_t *masks, int32_t nthreads)
+{
+    if (n <= 0 || k < 1 || k > 64 * W || R < 0) return OR_E_ARG;
+    int nt = nthreads_or_default(nthreads);
+    const int64_t P = 2 * (int64_t)R + 1;
+    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * (size_t)k);
+    if (!d) return OR_E_NOMEM;
+    int64_t bad_by_thread[MAX_THREADS] = {0};
+    cert_ctx cc = {n, row_ptr, col, k, S, R, W, P, dist, masks, d, bad_by_thread};
+    parallel_for(n, 4096, nt, cert_decode_body, &cc);
+    parallel_for(n, 1024, nt, cert_check_body, &cc);
+    int64_t bad = 0;
+    for (int t = 0; t < nt; t++) bad += bad_by_thread[t];
     free(d);
     return bad;
 }
@@ -348,6 +479,31 @@ static int64_t uf_find(int64_t *parent, int64_t x)
 }
 
 void oracle_free(void *p) { free(p); }
+
+typedef struct {
+    const int64_t *off;
+    int32_t *adj;
+    int64_t *fill;
+    int dedup;
+} sort_rows_ctx;
+
+static void sort_rows_body(int64_t lo, int64_t hi, int tid, void *p)
+{
+    (void)tid;
+    sort_rows_ctx *c = (sort_rows_ctx *)p;
+    for (int64_t v = lo; v < hi; v++) {
+        int32_t *row = c->adj + c->off[v];
+        int64_t len = c->off[v + 1] - c->off[v];
+        qsort(row, (size_t)len, sizeof(int32_t), cmp_i32);
+        if (c->dedup && len > 1) {
+            int64_t w = 1;
+            for (int64_t j = 1; j < len; j++)
+                if (row[j] != row[w - 1]) row[w++] = row[j];
+            len = w;
+        }
+        c->fill[v] = len;
+    }
+}
 
 int oracle_clean_csr(int64_t n_in, int64_t num_edges, const int64_t *src, const int64_t *dst,
                      uint32_t flags, int64_t *old_to_new, int64_t *n_out, int64_t *m_out,
@@ -384,19 +540,8 @@ int oracle_clean_csr(int64_t n_in, int64_t num_edges, const int64_t *src, const 
         if (sym) adj[fill[dst[e]]++] = (int32_t)src[e];
     }
     /* sort (and dedup) every row; fill[v] becomes the row's kept length */
-#pragma omp parallel for schedule(dynamic, 4096)
-    for (int64_t v = 0; v < n_in; v++) {
-        int32_t *row = adj + off[v];
-        int64_t len = off[v + 1] - off[v];
-        qsort(row, (size_t)len, sizeof(int32_t), cmp_i32);
-        if (dedup && len > 1) {
-            int64_t w = 1;
-            for (int64_t j = 1; j < len; j++)
-                if (row[j] != row[w - 1]) row[w++] = row[j];
-            len = w;
-        }
-        fill[v] = len;
-    }
+    sort_rows_ctx sc = {off, adj, fill, dedup};
+    parallel_for(n_in, 4096, nthreads_or_default(0), sort_rows_body, &sc);
     /* components (union-find over arcs, arcs taken as undirected) */
     char *keep = (char *)malloc((size_t)n_in);
     if (!keep) {

@@ -20,8 +20,10 @@ UNREACHED = 0xFFFFFFFF
 SYMBOLS = [
     "cbfs_status_string", "cbfs_last_error", "cbfs_build_csr", "cbfs_top_degree",
     "cbfs_select_clusters", "cbfs_run_batch_workspace_size", "cbfs_run_batch",
+    "cbfs_last_run_stats", "cbfs_profile_enable", "cbfs_profile_read",
     "cbfs_labels_pack", "cbfs_query_batch",
 ]
+KERNEL_KINDS = ["tiles", "init", "seed", "push", "pull", "finalize", "persistent", "labels", "query"]
 
 _lib = None
 
@@ -46,7 +48,14 @@ class _Tuning(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("group_words", ctypes.c_int32),
                 ("concurrent_groups", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("alpha", ctypes.c_float), ("beta", ctypes.c_float),
-                ("force_pull", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("force_pull", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _RunStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "groups", "group_words", "slots", "mode", "rounds", "push_rounds", "pull_rounds",
+        "frontier_vertices", "frontier_arcs", "device_error", "persistent_blocks")]
 
 
 class _Labels(ctypes.Structure):
@@ -64,10 +73,12 @@ class Tuning:
     alpha: float = 0.0
     beta: float = 0.0
     force_pull: int = 0
+    blocks_per_cu: int = 0
+    schedule: int = 0
 
     def _c(self) -> _Tuning:
         return _Tuning(self.mode, self.group_words, self.concurrent_groups, self.block_size,
-                       self.alpha, self.beta, self.force_pull, 0)
+                       self.alpha, self.beta, self.force_pull, self.blocks_per_cu, self.schedule, 0)
 
 
 def load():
@@ -97,6 +108,12 @@ def load():
     lib.cbfs_run_batch_workspace_size.restype = sz
     lib.cbfs_run_batch.argtypes = [P, P, P, P, P, P, P, sz, P]
     lib.cbfs_run_batch.restype = i32
+    lib.cbfs_last_run_stats.argtypes = [P]
+    lib.cbfs_last_run_stats.restype = i32
+    lib.cbfs_profile_enable.argtypes = [i32]
+    lib.cbfs_profile_enable.restype = i32
+    lib.cbfs_profile_read.argtypes = [P, P]
+    lib.cbfs_profile_read.restype = i32
     lib.cbfs_labels_pack.argtypes = [P, P, i32, i64, i32, P, P, P]
     lib.cbfs_labels_pack.restype = i32
     lib.cbfs_query_batch.argtypes = [P, i64, P, P, P, P]
@@ -186,6 +203,8 @@ def _dptr(t):
 def _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, tuning):
     cluster_ptr = np.ascontiguousarray(cluster_ptr, dtype=np.int32)
     sources = np.ascontiguousarray(sources, dtype=np.int32)
+    if cluster_ptr.size >= 1 and int(cluster_ptr[-1]) > sources.size:
+        raise ValueError("cluster_ptr[-1] exceeds the number of sources")
     g = _Csr(row_ptr_d.numel() - 1, col_d.numel(), row_ptr_d.data_ptr(), col_d.data_ptr())
     b = _Batch(cluster_ptr.size - 1, _np_ptr(cluster_ptr), _np_ptr(sources), int(R))
     t = tuning._c() if tuning is not None else None
@@ -262,3 +281,24 @@ def query_batch(dist_vm, mask_vm, R: int, s, t, out=None, stream=None):
     _check(load().cbfs_query_batch(ctypes.byref(L), q, _dptr(s), _dptr(t), _dptr(ans), _stream_ptr(stream)),
            "cbfs_query_batch")
     return ans
+
+
+def last_run_stats() -> dict:
+    """``cbfs_last_run_stats`` of this thread's last run_batch (waits for it)."""
+    r = _RunStats()
+    _check(load().cbfs_last_run_stats(ctypes.byref(r)), "cbfs_last_run_stats")
+    return {name: int(getattr(r, name)) for name, _t in _RunStats._fields_}
+
+
+def profile_enable(on: bool = True):
+    """``cbfs_profile_enable``: time every kernel launch of this thread with HIP events."""
+    _check(load().cbfs_profile_enable(1 if on else 0), "cbfs_profile_enable")
+
+
+def profile_read() -> dict:
+    """``cbfs_profile_read``: {kernel kind: (launches, total ms)} for the recorded launches."""
+    n = len(KERNEL_KINDS)
+    launches = (ctypes.c_int64 * n)()
+    ms = (ctypes.c_double * n)()
+    _check(load().cbfs_profile_read(launches, ms), "cbfs_profile_read")
+    return {KERNEL_KINDS[k]: (int(launches[k]), float(ms[k])) for k in range(n)}

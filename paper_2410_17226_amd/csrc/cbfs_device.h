@@ -31,9 +31,12 @@ namespace cbfs {
 constexpr int BLOCK = 256;          // threads per block (4 waves of 64)
 constexpr int WAVES = BLOCK / 64;
 constexpr int PIECE = 256;          // max arcs per frontier work item (push)
-constexpr int TILE_ITEMS = 2048;    // merge-path items (rows + arcs) per pull block
+constexpr int TILE_ITEMS = 4096;    // merge-path items (rows + arcs) per pull block
 constexpr int IPT = TILE_ITEMS / BLOCK;
-constexpr int STAGE_CAP = 1024;     // LDS frontier staging capacity per block
+// a pull block claims at most one vertex per row end it consumes plus one
+// partial row per thread
+constexpr int PULL_STAGE_CAP = TILE_ITEMS / 2 + BLOCK + 64;
+constexpr int STAGE_CAP = 1024;     // LDS frontier staging capacity per push/seed block
 constexpr int MAX_W = 8;            // max words per vertex in a group
 constexpr uint32_t UNREACHED = 0xFFFFFFFFu;
 constexpr int32_t E_RADIUS = -5;
@@ -242,94 +245,6 @@ __device__ __forceinline__ void vertex_phase(const SlotArgs &s, const GroupDesc 
         if (j < g.nc) emit_cluster<WC>(o, n, g.c0 + j, u, round, sv + j * WC, nw + j * WC, g.full + j * WC);
 }
 
-// ---------------------------------------------------------------------------
-// LDS-staged frontier queue: claimed vertices are collected in LDS and
-// appended to the global queue with one atomic per flush, expanded into their
-// PIECE-sized work items.
-// ---------------------------------------------------------------------------
-struct Stager {
-    int32_t v[STAGE_CAP];
-    int32_t deg[STAGE_CAP];
-    int32_t poff[STAGE_CAP];
-    int32_t count;
-    int32_t pieces;
-    unsigned long long degsum;
-    long long base;
-};
-
-__device__ __forceinline__ void stager_init(Stager &st)
-{
-    if (threadIdx.x == 0) {
-        st.count = 0;
-        st.pieces = 0;
-        st.degsum = 0;
-    }
-}
-
-__device__ __forceinline__ void stager_push(Stager &st, int32_t v, int32_t deg)
-{
-    const int slot = atomicAdd(&st.count, 1);
-    const int po = atomicAdd(&st.pieces, pieces_of(deg));
-    st.v[slot] = v;
-    st.deg[slot] = deg;
-    st.poff[slot] = po;
-    atomicAdd(&st.degsum, (unsigned long long)deg);
-}
-
-// Block-uniform call (every thread, after a barrier).
-__device__ __forceinline__ void stager_flush(Stager &st, int64_t *q_next, unsigned long long *ctr_next)
-{
-    __syncthreads();
-    const int cnt = st.count;
-    if (cnt == 0) return;
-    if (threadIdx.x == 0) {
-        st.base = (long long)atomicAdd(ctr_next + 0, (unsigned long long)st.pieces);
-        atomicAdd(ctr_next + 1, (unsigned long long)cnt);
-        atomicAdd(ctr_next + 2, st.degsum);
-    }
-    __syncthreads();
-    const long long base = st.base;
-    for (int k = threadIdx.x; k < cnt; k += BLOCK) {
-        const int32_t v = st.v[k];
-        const int pc = pieces_of(st.deg[k]);
-        int64_t *dst = q_next + base + st.poff[k];
-        for (int p = 0; p < pc; p++) dst[p] = ((int64_t)p << 32) | (int64_t)(uint32_t)v;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        st.count = 0;
-        st.pieces = 0;
-        st.degsum = 0;
-    }
-    __syncthreads();
-}
-
-// Claim v for F_{i+1} (the compare-and-swap on r[v] of Algorithm "Cluster-BFS
-// search from S", here an atomic OR on a membership bitmap: first setter wins).
-__device__ __forceinline__ void claim(Stager &st, uint64_t *bits_next, int32_t v, int32_t deg)
-{
-    const unsigned long long bit = 1ull << (v & 63);
-    const unsigned long long old = atomicOr(reinterpret_cast<unsigned long long *>(bits_next + (v >> 6)), bit);
-    if (!(old & bit)) stager_push(st, v, deg);
-}
-
-// Contribute x (bits of a neighbour's set) to v: OR the bits not yet in
-// Seen_i(v) into nxt(v); claim v if this call added any of them.
-template <int W>
-__device__ __forceinline__ void contribute(Stager &st, uint64_t *nxt, uint64_t *bits_next,
-                                          const int32_t *row_ptr, int32_t v, const uint64_t (&x)[W])
-{
-    uint64_t *p = nxt + (size_t)v * W;
-    uint64_t added = 0;
-#pragma unroll
-    for (int w = 0; w < W; w++)
-        if (x[w]) {
-            const uint64_t old = or64(p + w, x[w]);
-            added |= x[w] & ~old;
-        }
-    if (added) claim(st, bits_next, v, row_ptr[v + 1] - row_ptr[v]);
-}
-
 // Exclusive block scan of one int per thread; *total receives the sum.
 __device__ __forceinline__ int block_exclusive_scan(int x, int *tmp /*[WAVES+1]*/, int *total)
 {
@@ -356,6 +271,102 @@ __device__ __forceinline__ int block_exclusive_scan(int x, int *tmp /*[WAVES+1]*
     const int r = v - x + tmp[wid];
     __syncthreads();
     return r;
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged frontier queue: claimed vertices are collected in LDS and
+// appended to the global queue with one atomic per flush, expanded into their
+// PIECE-sized work items (offsets from a block scan at flush time).
+// ---------------------------------------------------------------------------
+template <int CAP>
+struct Stager {
+    int32_t v[CAP];
+    int32_t count;
+    unsigned long long degsum;
+    long long base;
+    int tmp[WAVES + 1];
+};
+
+template <int CAP>
+__device__ __forceinline__ void stager_init(Stager<CAP> &st)
+{
+    if (threadIdx.x == 0) {
+        st.count = 0;
+        st.degsum = 0;
+    }
+}
+
+template <int CAP>
+__device__ __forceinline__ void stager_push(Stager<CAP> &st, int32_t v, int32_t deg)
+{
+    const int slot = atomicAdd(&st.count, 1);
+    st.v[slot] = v;
+    atomicAdd(&st.degsum, (unsigned long long)deg);
+}
+
+// Block-uniform call (every thread).
+template <int CAP>
+__device__ __forceinline__ void stager_flush(Stager<CAP> &st, const int32_t *row_ptr, int64_t *q_next,
+                                             unsigned long long *ctr_next)
+{
+    __syncthreads();
+    const int cnt = st.count;
+    if (cnt == 0) return;
+    const int per = (cnt + BLOCK - 1) / BLOCK;
+    const int lo = threadIdx.x * per < cnt ? threadIdx.x * per : cnt;
+    const int hi = lo + per < cnt ? lo + per : cnt;
+    int mine = 0;
+    for (int k = lo; k < hi; k++) {
+        const int32_t v = st.v[k];
+        mine += pieces_of(row_ptr[v + 1] - row_ptr[v]);
+    }
+    int total;
+    const int off = block_exclusive_scan(mine, st.tmp, &total);
+    if (threadIdx.x == 0) {
+        st.base = (long long)atomicAdd(ctr_next + 0, (unsigned long long)total);
+        atomicAdd(ctr_next + 1, (unsigned long long)cnt);
+        atomicAdd(ctr_next + 2, st.degsum);
+    }
+    __syncthreads();
+    int64_t *dst = q_next + st.base + off;
+    for (int k = lo; k < hi; k++) {
+        const int32_t v = st.v[k];
+        const int pc = pieces_of(row_ptr[v + 1] - row_ptr[v]);
+        for (int p = 0; p < pc; p++) *dst++ = ((int64_t)p << 32) | (int64_t)(uint32_t)v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st.count = 0;
+        st.degsum = 0;
+    }
+    __syncthreads();
+}
+
+// Claim v for F_{i+1} (the compare-and-swap on r[v] of Algorithm "Cluster-BFS
+// search from S", here an atomic OR on a membership bitmap: first setter wins).
+template <int CAP>
+__device__ __forceinline__ void claim(Stager<CAP> &st, uint64_t *bits_next, int32_t v, int32_t deg)
+{
+    const unsigned long long bit = 1ull << (v & 63);
+    const unsigned long long old = atomicOr(reinterpret_cast<unsigned long long *>(bits_next + (v >> 6)), bit);
+    if (!(old & bit)) stager_push(st, v, deg);
+}
+
+// Contribute x (bits of a neighbour's set) to v: OR the bits not yet in
+// Seen_i(v) into nxt(v); claim v if this call added any of them.
+template <int W, int CAP>
+__device__ __forceinline__ void contribute(Stager<CAP> &st, uint64_t *nxt, uint64_t *bits_next,
+                                          const int32_t *row_ptr, int32_t v, const uint64_t (&x)[W])
+{
+    uint64_t *p = nxt + (size_t)v * W;
+    uint64_t added = 0;
+#pragma unroll
+    for (int w = 0; w < W; w++)
+        if (x[w]) {
+            const uint64_t old = or64(p + w, x[w]);
+            added |= x[w] & ~old;
+        }
+    if (added) claim(st, bits_next, v, row_ptr[v + 1] - row_ptr[v]);
 }
 
 }  // namespace cbfs

@@ -2,6 +2,8 @@
 #pragma once
 #include <cstdint>
 
+#include <hip/hip_runtime.h>
+
 #include "cbfs.h"
 
 namespace cbfs {
@@ -10,5 +12,8 @@ namespace cbfs {
 cbfs_status fail(cbfs_status s, const char *msg);
 // Records a formatted HIP failure ("<what>: <hip error string>") and returns CBFS_E_HIP.
 cbfs_status hip_fail(const char *what, int hip_error);
+// Kernel timing hooks (no-ops unless cbfs_profile_enable(1) was called).
+void prof_begin(int kind, hipStream_t st, void **token);
+void prof_end(void *token);
 
 }  // namespace cbfs

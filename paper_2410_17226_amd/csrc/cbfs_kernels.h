@@ -9,6 +9,28 @@
 
 namespace cbfs {
 
+constexpr int MAX_SLOTS = 64;  // group slots searched side by side in one persistent launch
+constexpr int GRAB = 4;        // work items a persistent block takes per counter update
+
+// Arguments of the persistent batch kernel (all pointers are device memory).
+struct PersistArgs {
+    GraphArgs gr;
+    OutArgs o;
+    const SlotArgs *slots;      // [num_slots]
+    const GroupDesc *groups;    // [num_groups]
+    int32_t num_groups, num_slots;
+    const int32_t *sources;     // batch sources
+    const int32_t *cluster_ptr; // batch cluster_ptr
+    unsigned int *bar;          // [2] grid barrier: arrivals, generation
+    unsigned long long *work;   // [3] per-round work counters
+    int32_t *err;               // 0 ok, 1 barrier timeout, 2 round limit
+    long long *stats;           // [num_groups][5]: rounds, push, pull, sum |F|, sum deg(F)
+    float alpha, beta;
+    int32_t force_pull;
+    int32_t schedule;           // 0 shared work counter, 1 fixed stride
+    int64_t max_rounds;
+};
+
 hipError_t launch_tiles(const int32_t *row_ptr, int64_t n, int64_t m, int32_t ntiles, int32_t *tile_row,
                         int32_t *tile_edge, hipStream_t st);
 hipError_t launch_init(int W, const SlotArgs &s, int64_t n, const GroupDesc &g, const OutArgs &o, hipStream_t st);
@@ -17,8 +39,12 @@ hipError_t launch_seed(int W, int WC, const SlotArgs &s, const GraphArgs &gr, co
 hipError_t launch_push(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                        const OutArgs &o, int32_t round, int64_t nq, hipStream_t st);
 hipError_t launch_pull(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                       const OutArgs &o, int32_t round, int64_t nq, hipStream_t st);
+                       const OutArgs &o, int32_t round, hipStream_t st);
 hipError_t launch_finalize(int W, int WC, const SlotArgs &s, int64_t n, const GroupDesc &g, const OutArgs &o,
                            hipStream_t st);
+// Blocks of the persistent kernel on the current device: per_cu per compute
+// unit (0 = as many as can be resident), capped at what can be resident.
+hipError_t persistent_grid(int W, int WC, int per_cu, int *blocks);
+hipError_t launch_persistent(int W, int WC, const PersistArgs &a, int blocks, hipStream_t st);
 
 }  // namespace cbfs

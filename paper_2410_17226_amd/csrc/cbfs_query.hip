@@ -84,8 +84,11 @@ extern "C" cbfs_status cbfs_labels_pack(const uint32_t *dist, const uint64_t *ma
         return fail(CBFS_E_ARG, "cbfs_labels_pack: bad argument");
     const int64_t total = (int64_t)num_clusters * n;
     const int blocks = (int)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
+    void *tok;
+    prof_begin(CBFS_KERNEL_LABELS, (hipStream_t)stream, &tok);
     k_labels_pack<<<blocks, 256, 0, (hipStream_t)stream>>>(dist, masks, num_clusters, n, radius, dist_vm, mask_vm);
     hipError_t e = hipGetLastError();
+    prof_end(tok);
     return e == hipSuccess ? CBFS_OK : hip_fail("labels_pack", e);
 }
 
@@ -97,8 +100,11 @@ extern "C" cbfs_status cbfs_query_batch(const cbfs_labels *L, int64_t q, const i
         return fail(CBFS_E_ARG, "cbfs_query_batch: bad argument");
     if (q == 0) return CBFS_OK;
     const int64_t blocks = (q * 64 + 255) / 256;
+    void *tok;
+    prof_begin(CBFS_KERNEL_QUERY, (hipStream_t)stream, &tok);
     k_query<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(L->n, L->num_clusters, L->radius, L->dist_vm,
                                                                  L->mask_vm, q, s, t, ans);
     hipError_t e = hipGetLastError();
+    prof_end(tok);
     return e == hipSuccess ? CBFS_OK : hip_fail("query", e);
 }

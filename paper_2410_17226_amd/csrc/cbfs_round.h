@@ -1,0 +1,308 @@
+// Round work of the Cluster-BFS level loop as block-level device functions,
+// shared by the one-launch-per-round kernels and the persistent kernel.
+//
+// Every function below that contains a barrier is block-uniform: all threads
+// of the block call it with the same arguments.
+#pragma once
+#include "cbfs_device.h"
+
+namespace cbfs {
+
+template <int W>
+struct PushSmem {
+    int scan[BLOCK + 1];
+    int32_t estart[BLOCK];
+    uint64_t cu[BLOCK * W];
+    int tmp[WAVES + 1];
+    Stager<STAGE_CAP> st;
+};
+
+struct PullSmem {
+    Stager<PULL_STAGE_CAP> st;
+};
+
+template <int W>
+union RoundSmem {
+    PushSmem<W> push;
+    PullSmem pull;
+};
+
+// Init (Algorithm "Cluster-BFS search from S", initialization): clear one
+// group slot; the group's cluster statuses to CBFS_OK.  Grid-stride part
+// [tid, .., stride).
+template <int W>
+__device__ __forceinline__ void init_part(const SlotArgs &s, int64_t n, const GroupDesc &g, const OutArgs &o,
+                                          int64_t tid, int64_t stride)
+{
+    const int64_t words = n * W;
+    for (int64_t k = tid; k < words; k += stride) {
+        s.A[k] = 0;
+        s.B[k] = 0;
+        s.seen[k] = 0;
+    }
+    for (int64_t k = tid; k < s.nwords; k += stride) {
+        s.bits0[k] = 0;
+        s.bits1[k] = 0;
+        s.bits2[k] = 0;
+    }
+    if (tid < 12) s.ctr[tid] = 0;
+    if (tid < g.nc) o.status[g.c0 + tid] = 0;
+}
+
+// Clear the bitmap and counters of round i+2 (they last served round i-1).
+__device__ __forceinline__ void clear_ahead_part(const SlotArgs &s, int32_t round, int64_t tid, int64_t stride)
+{
+    uint64_t *clr = bits_buf(s, (round + 2) % 3);
+    for (int64_t k = tid; k < s.nwords; k += stride) clr[k] = 0;
+    if (tid < 4) ctr_buf(s, round + 2)[tid] = 0;
+}
+
+// Seed (one block): bit i of cluster j at its source s_i, i.e. Seen_0; and
+// F_0 = the sources.  sources/cluster_ptr are the batch arrays on the device.
+template <int W, int WC>
+__device__ void seed_block(Stager<STAGE_CAP> &st, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
+                           const int32_t *sources, const int32_t *cluster_ptr)
+{
+    __syncthreads();
+    stager_init(st);
+    __syncthreads();
+    const int32_t first = cluster_ptr[g.c0];
+    const int32_t total = cluster_ptr[g.c0 + g.nc] - first;
+    for (int32_t k = threadIdx.x; k < total; k += BLOCK) {
+        const int32_t idx = first + k;
+        int32_t j = 0;
+        while (cluster_ptr[g.c0 + j + 1] <= idx) j++;
+        const int32_t i = idx - cluster_ptr[g.c0 + j];
+        const int32_t v = sources[idx];
+        or64(s.A + (size_t)v * W + j * WC + (i >> 6), 1ull << (i & 63));
+        claim(st, s.bits0, v, gr.row_ptr[v + 1] - gr.row_ptr[v]);
+    }
+    stager_flush(st, gr.row_ptr, s.q0, s.ctr + 0);
+}
+
+// ---------------------------------------------------------------------------
+// Round i, push direction (EdgeMap-Sparse), one chunk of BLOCK queue entries
+// (pieces of <= PIECE arcs): the vertex phase for first pieces, then the
+// chunk's arcs spread evenly over the block (block scan + binary search of
+// each arc's owner).  Per arc (u, v): x = Seen_i(u) \ Seen_i(v); if not empty,
+// 64-bit atomic OR into nxt(v) and claim v (the Fetch_And_Or and
+// compare_and_swap of the paper's edge phase).
+// ---------------------------------------------------------------------------
+template <int W, int WC>
+__device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
+                           const OutArgs &o, int32_t round, int64_t nq, int64_t chunk)
+{
+    const int64_t first = chunk * BLOCK;
+    if (first >= nq) return;  // block-uniform
+    __syncthreads();
+    stager_init(sm.st);
+    const uint64_t *cur = cur_buf(s, round);
+    uint64_t *nxt = nxt_buf(s, round);
+    uint64_t *bits_next = bits_buf(s, (round + 1) % 3);
+    int64_t *q_next = q_buf(s, round + 1);
+    unsigned long long *ctr_next = ctr_buf(s, round + 1);
+
+    int cnt = 0;
+    const int64_t idx = first + threadIdx.x;
+    if (idx < nq) {
+        const int64_t e = q_buf(s, round)[idx];
+        const int32_t u = (int32_t)(e & 0xffffffff);
+        const int32_t p = (int32_t)(e >> 32);
+        const int32_t rs = gr.row_ptr[u], re = gr.row_ptr[u + 1];
+        const int32_t lo = rs + p * PIECE;
+        const int32_t hi = re < lo + PIECE ? re : lo + PIECE;
+        cnt = hi > lo ? hi - lo : 0;
+        uint64_t cu[W];
+        load_words<W>(cur + (size_t)u * W, cu);
+        if (p == 0) vertex_phase<W, WC>(s, g, o, gr.n, round, u, cu);
+        sm.estart[threadIdx.x] = lo;
+#pragma unroll
+        for (int w = 0; w < W; w++) sm.cu[threadIdx.x * W + w] = cu[w];
+    }
+    int total;
+    const int off = block_exclusive_scan(cnt, sm.tmp, &total);
+    sm.scan[threadIdx.x] = off;
+    if (threadIdx.x == 0) sm.scan[BLOCK] = total;
+    __syncthreads();
+
+    for (int base = 0; base < total; base += BLOCK) {
+        const int e = base + threadIdx.x;
+        if (e < total) {
+            // owner: last j with scan[j] <= e (entries with no arcs share offsets)
+            int lo = 0, hi = BLOCK;
+            while (hi - lo > 1) {
+                int mid = (lo + hi) >> 1;
+                if (sm.scan[mid] <= e) lo = mid;
+                else hi = mid;
+            }
+            const int32_t v = gr.col[sm.estart[lo] + (e - sm.scan[lo])];
+            uint64_t cv[W], x[W];
+            load_words<W>(cur + (size_t)v * W, cv);
+            bool any = false;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                x[w] = sm.cu[lo * W + w] & ~cv[w];
+                any |= x[w] != 0;
+            }
+            if (any) contribute<W>(sm.st, nxt, bits_next, gr.row_ptr, v, x);
+        }
+        __syncthreads();
+        if (sm.st.count > STAGE_CAP - BLOCK) stager_flush(sm.st, gr.row_ptr, q_next, ctr_next);
+    }
+    stager_flush(sm.st, gr.row_ptr, q_next, ctr_next);
+}
+
+// ---------------------------------------------------------------------------
+// Round i, pull direction (EdgeMap-Dense), one merge-path tile of TILE_ITEMS
+// items (arcs and row ends) of the CSR.  Each thread walks IPT consecutive
+// items row segment by row segment.  For a row v it loads Seen_i(v) once (a
+// finished row, holding every source, is skipped: EdgeMap's Cond_F), then
+// processes its arcs in batches: the frontier bits of all neighbours in the
+// batch, then Seen_i(u) of all of them, are requested together
+// (unconditional loads with a select, so the loads overlap), and the new bits
+// are OR-ed into a register accumulator; the row stops once the accumulator
+// completes the set (EdgeMap-Dense's break).  At the row's end, or where the
+// thread's items run out, the bits not yet in Seen_i(v) are merged into
+// nxt(v) with atomics (a row may span threads and tiles).  The thread
+// consuming a row's end item also runs the vertex phase for that row if it is
+// in F_i, so that phase is coalesced across the tile's rows.
+// ---------------------------------------------------------------------------
+template <int W>
+constexpr int pull_batch()
+{
+    return W <= 2 ? 8 : (W <= 4 ? 4 : 2);
+}
+
+template <int W, int WC>
+__device__ void pull_tile(PullSmem &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
+                          const OutArgs &o, int32_t round, int32_t t)
+{
+    constexpr int NB = pull_batch<W>();
+    const uint64_t *cur = cur_buf(s, round);
+    uint64_t *nxt = nxt_buf(s, round);
+    const uint64_t *bits_cur = bits_buf(s, round % 3);
+    uint64_t *bits_next = bits_buf(s, (round + 1) % 3);
+    const int32_t *row_end = gr.row_ptr + 1;
+
+    const int32_t r0 = gr.tile_row[t], e0 = gr.tile_edge[t];
+    const int32_t r1 = gr.tile_row[t + 1], e1 = gr.tile_edge[t + 1];
+    __syncthreads();
+    stager_init(sm.st);
+    __syncthreads();
+
+    // this thread's merge-path start inside the tile
+    const int32_t tile_rows = r1 - r0, tile_edges = e1 - e0;
+    const int32_t tile_items = tile_rows + tile_edges;
+    int32_t rel = (int32_t)threadIdx.x * IPT;
+    if (rel > tile_items) rel = tile_items;
+    int32_t my_end = ((int32_t)threadIdx.x + 1) * IPT;
+    if (my_end > tile_items) my_end = tile_items;
+    int32_t row, edge;
+    {
+        int32_t lo = rel > tile_edges ? rel - tile_edges : 0;
+        int32_t hi = rel < tile_rows ? rel : tile_rows;
+        while (lo < hi) {
+            int32_t mid = (lo + hi) >> 1;
+            if (row_end[r0 + mid] - e0 <= rel - mid - 1) lo = mid + 1;
+            else hi = mid;
+        }
+        row = r0 + lo;
+        edge = e0 + (rel - lo);
+    }
+
+    uint64_t full[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) full[w] = g.full[w];
+
+    while (rel < my_end) {
+        const int32_t rend = row_end[row];
+        const int32_t budget = my_end - rel;
+        const int32_t seg_end = rend < edge + budget ? rend : edge + budget;
+        uint64_t cv[W], acc[W];
+        load_words<W>(cur + (size_t)row * W, cv);
+        bool fin = true;
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            acc[w] = 0;
+            fin &= cv[w] == full[w];
+        }
+        for (int32_t e = edge; e < seg_end && !fin; e += NB) {
+            int32_t u[NB];
+            bool hit[NB];
+#pragma unroll
+            for (int j = 0; j < NB; j++) u[j] = (e + j < seg_end) ? gr.col[e + j] : row;
+            uint64_t bw[NB];
+#pragma unroll
+            for (int j = 0; j < NB; j++) bw[j] = bits_cur[u[j] >> 6];
+#pragma unroll
+            for (int j = 0; j < NB; j++) hit[j] = ((bw[j] >> (u[j] & 63)) & 1ull) && (e + j < seg_end);
+            uint64_t cu[NB][W];
+#pragma unroll
+            for (int j = 0; j < NB; j++) load_words<W>(cur + (size_t)(hit[j] ? u[j] : row) * W, cu[j]);
+            bool f = true;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+#pragma unroll
+                for (int j = 0; j < NB; j++) acc[w] |= hit[j] ? (cu[j][w] & ~cv[w]) : 0ull;
+                f &= (acc[w] | cv[w]) == full[w];
+            }
+            fin = f;
+        }
+        rel += seg_end - edge;
+        edge = seg_end;
+        bool any = false;
+#pragma unroll
+        for (int w = 0; w < W; w++) any |= acc[w] != 0;
+        if (any) contribute<W>(sm.st, nxt, bits_next, gr.row_ptr, row, acc);
+        if (edge == rend && rel < my_end) {
+            // the row's end item is ours: vertex phase if the row is in F_i
+            if ((bits_cur[row >> 6] >> (row & 63)) & 1ull) vertex_phase<W, WC>(s, g, o, gr.n, round, row, cv);
+            rel++;
+            row++;
+        } else {
+            break;  // items exhausted inside this row
+        }
+    }
+    stager_flush(sm.st, gr.row_ptr, q_buf(s, round + 1), ctr_buf(s, round + 1));
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: a vertex never reached by the center gets CBFS_UNREACHED and zero
+// masks (a cluster source reaching it is a radius violation); a vertex reached
+// by the center but not by every source of the cluster is a violation too.
+// ---------------------------------------------------------------------------
+template <int W, int WC>
+__device__ __forceinline__ void finalize_part(const SlotArgs &s, int64_t n, const GroupDesc &g, const OutArgs &o,
+                                              int64_t tid, int64_t stride)
+{
+    const int64_t P = 2 * (int64_t)o.R + 1;
+    for (int64_t v = tid; v < n; v += stride) {
+        uint64_t sv[W];
+        load_words<W>(s.seen + (size_t)v * W, sv);
+#pragma unroll
+        for (int j = 0; j < W / WC; j++) {
+            if (j >= g.nc) break;
+            const int32_t c = g.c0 + j;
+            const uint64_t *sc = sv + j * WC;
+            bool any = false, full = true;
+#pragma unroll
+            for (int x = 0; x < WC; x++) {
+                any |= sc[x] != 0;
+                full &= sc[x] == g.full[j * WC + x];
+            }
+            if (!(sc[0] & 1ull)) {
+                if (any) atomicExch(o.status + c, E_RADIUS);
+                o.dist[(size_t)c * n + v] = UNREACHED;
+                for (int64_t p = 0; p < P; p++) {
+                    uint64_t *dst = o.masks + (((size_t)c * P + p) * (size_t)n + (size_t)v) * WC;
+#pragma unroll
+                    for (int x = 0; x < WC; x++) dst[x] = 0;
+                }
+            } else if (!full) {
+                atomicExch(o.status + c, E_RADIUS);
+            }
+        }
+    }
+}
+
+}  // namespace cbfs

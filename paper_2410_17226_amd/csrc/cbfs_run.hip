@@ -1,6 +1,10 @@
-// cbfs_run_batch: argument checks, workspace layout, cluster grouping and the
-// host-driven level loop (Algorithm "Cluster-BFS search from S": init, then
-// rounds of vertex phase + edge phase until the frontier is empty).
+// cbfs_run_batch: argument checks, workspace layout, cluster grouping, and the
+// two drivers of the level loop (Algorithm "Cluster-BFS search from S": init,
+// then rounds of vertex phase + edge phase until the frontier is empty):
+//   - host loop: one launch per round, the frontier counters read back each
+//     round to choose the direction and to stop;
+//   - persistent: one cooperative launch for the whole batch.
+// Also the per-thread diagnostics (run statistics and kernel timing).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +24,48 @@ thread_local std::string g_last_error;
 
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// ---- diagnostics ----------------------------------------------------------
+struct ProfRecord {
+    int kind;
+    hipEvent_t start, stop;
+};
+thread_local bool g_prof_on = false;
+thread_local std::vector<ProfRecord> g_prof;
+thread_local int64_t g_prof_launches[CBFS_KERNEL_KINDS];
+thread_local double g_prof_ms[CBFS_KERNEL_KINDS];
+
+struct LastRun {
+    bool valid = false;
+    bool device_stats = false;
+    hipStream_t stream = nullptr;
+    const long long *stats = nullptr;  // device [groups][5] (persistent mode)
+    const int32_t *err = nullptr;      // device error flag (persistent mode)
+    cbfs_run_stats host{};
+};
+thread_local LastRun g_last;
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+    int kind;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(int k, hipStream_t s) : kind(k), st(s)
+    {
+        if (!g_prof_on) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            a = b = nullptr;
+            return;
+        }
+        hipEventRecord(a, st);
+    }
+    ~ProfScope()
+    {
+        if (!a) return;
+        hipEventRecord(b, st);
+        g_prof.push_back({kind, a, b});
+    }
+};
 }  // namespace
 
 cbfs_status fail(cbfs_status s, const char *msg)
@@ -34,8 +80,18 @@ cbfs_status hip_fail(const char *what, int err)
     return CBFS_E_HIP;
 }
 
+void prof_begin(int kind, hipStream_t st, void **token)
+{
+    *token = nullptr;
+    if (!g_prof_on) return;
+    *token = new ProfScope(kind, st);
+}
+
+void prof_end(void *token) { delete (ProfScope *)token; }
+
 // How a batch is laid out: W words per vertex per group, WC words per cluster,
-// clusters packed W/WC per group in batch order.
+// clusters packed W/WC per group in batch order; `slots` groups searched side
+// by side in the persistent mode.
 struct Plan {
     int64_t n = 0, m = 0;
     int32_t C = 0, R = 0;
@@ -44,15 +100,18 @@ struct Plan {
     int32_t per_group = 1;
     int32_t groups = 0;
     int32_t slots = 1;
-    int32_t mode = CBFS_MODE_HOST_LOOP;
+    int32_t mode = CBFS_MODE_PERSISTENT;
     float alpha = 15.0f, beta = 20.0f;
     int32_t force_pull = 0;
+    int32_t blocks_per_cu = 0, schedule = 0;
     int32_t ntiles = 0;
     int64_t nwords = 0;
     int64_t qcap = 0;
     int32_t total_sources = 0;
     // workspace offsets
-    size_t off_tiles_row = 0, off_tiles_edge = 0, off_cptr = 0, off_src = 0, off_slots = 0, slot_bytes = 0;
+    size_t off_tiles_row = 0, off_tiles_edge = 0, off_cptr = 0, off_src = 0;
+    size_t off_slotdesc = 0, off_groupdesc = 0, off_ctl = 0, off_stats = 0;
+    size_t off_slots = 0, slot_bytes = 0;
     size_t total = 0;
 };
 
@@ -98,22 +157,29 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
     p.R = b->radius;
     p.total_sources = b->cluster_ptr[p.C];
     p.WC = (kmax + 63) / 64;
-    // defaults
-    p.W = p.WC == 3 ? 3 : 4;
+    // defaults: wide groups share one CSR pass among many clusters; sparse
+    // (high-diameter) graphs get narrow groups searched side by side
+    const bool sparse = p.m < 8 * p.n;
+    p.W = p.WC == 3 ? 3 : (sparse ? p.WC : 8);
     if (p.W < p.WC) p.W = p.WC;
-    p.mode = CBFS_MODE_HOST_LOOP;
+    p.mode = sparse ? CBFS_MODE_PERSISTENT : CBFS_MODE_HOST_LOOP;
+    int32_t want_slots = 0;
     if (t) {
         if (t->mode < 0 || t->mode > CBFS_MODE_PERSISTENT) return fail(CBFS_E_ARG, "cbfs_tuning: bad mode");
-        if (t->mode == CBFS_MODE_PERSISTENT)
-            return fail(CBFS_E_ARG, "cbfs_tuning: persistent mode not available in this build");
         if (t->mode != CBFS_MODE_AUTO) p.mode = t->mode;
         if (t->group_words != 0) p.W = t->group_words;
         if (t->block_size != 0 && t->block_size != BLOCK) return fail(CBFS_E_ARG, "cbfs_tuning: block_size must be 256");
         if (t->alpha != 0.0f) p.alpha = t->alpha;
-        if (t->beta != 0.0f) p.beta = t->beta;
         if (t->beta < 0.0f) return fail(CBFS_E_ARG, "cbfs_tuning: beta < 0");
+        if (t->beta != 0.0f) p.beta = t->beta;
         p.force_pull = t->force_pull;
-        if (t->concurrent_groups < 0) return fail(CBFS_E_ARG, "cbfs_tuning: concurrent_groups < 0");
+        if (t->concurrent_groups < 0 || t->concurrent_groups > MAX_SLOTS)
+            return fail(CBFS_E_ARG, "cbfs_tuning: concurrent_groups outside [0, 64]");
+        want_slots = t->concurrent_groups;
+        if (t->blocks_per_cu < 0 || t->blocks_per_cu > 32) return fail(CBFS_E_ARG, "cbfs_tuning: blocks_per_cu");
+        if (t->schedule < 0 || t->schedule > 1) return fail(CBFS_E_ARG, "cbfs_tuning: schedule must be 0 or 1");
+        p.blocks_per_cu = t->blocks_per_cu;
+        p.schedule = t->schedule;
     }
     if (!valid_w(p.W, p.WC))
         return fail(CBFS_E_ARG, "cbfs_tuning: group_words must be one of 1,2,4,8 and a multiple of the cluster words");
@@ -124,21 +190,31 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
         p.per_group = p.W / p.WC;
     }
     p.groups = (p.C + p.per_group - 1) / p.per_group;
-    p.slots = 1;
+    if (p.mode == CBFS_MODE_PERSISTENT) {
+        int32_t sl = want_slots ? want_slots : (sparse ? 32 : 1);
+        p.slots = std::max(1, std::min(sl, p.groups));
+    } else {
+        p.slots = 1;
+    }
     p.nwords = (p.n + 63) / 64;
     p.qcap = p.n + p.m / PIECE + 1;
     p.ntiles = (int32_t)((p.n + p.m + TILE_ITEMS - 1) / TILE_ITEMS);
     if (p.ntiles < 1) p.ntiles = 1;
 
     size_t off = 0;
-    p.off_tiles_row = off;
-    off = align_up(off + sizeof(int32_t) * (size_t)(p.ntiles + 1));
-    p.off_tiles_edge = off;
-    off = align_up(off + sizeof(int32_t) * (size_t)(p.ntiles + 1));
-    p.off_cptr = off;
-    off = align_up(off + sizeof(int32_t) * (size_t)(p.C + 1));
-    p.off_src = off;
-    off = align_up(off + sizeof(int32_t) * (size_t)std::max(1, p.total_sources));
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    p.off_tiles_row = take(sizeof(int32_t) * (size_t)(p.ntiles + 1));
+    p.off_tiles_edge = take(sizeof(int32_t) * (size_t)(p.ntiles + 1));
+    p.off_cptr = take(sizeof(int32_t) * (size_t)(p.C + 1));
+    p.off_src = take(sizeof(int32_t) * (size_t)std::max(1, p.total_sources));
+    p.off_slotdesc = take(sizeof(SlotArgs) * MAX_SLOTS);
+    p.off_groupdesc = take(sizeof(GroupDesc) * (size_t)p.groups);
+    p.off_ctl = take(64 + sizeof(unsigned long long) * 3);
+    p.off_stats = take(sizeof(long long) * 5 * (size_t)p.groups);
     p.off_slots = off;
     size_t sb = 0;
     sb += 3 * align_up(sizeof(uint64_t) * (size_t)p.n * p.W);
@@ -196,6 +272,19 @@ static GroupDesc group_desc(const Plan &p, const cbfs_batch *b, int32_t grp)
     return d;
 }
 
+static GraphArgs graph_args(const Plan &p, const cbfs_csr *g, char *ws)
+{
+    GraphArgs gr{};
+    gr.n = p.n;
+    gr.m = p.m;
+    gr.row_ptr = g->row_ptr;
+    gr.col = g->col;
+    gr.tile_row = (const int32_t *)(ws + p.off_tiles_row);
+    gr.tile_edge = (const int32_t *)(ws + p.off_tiles_edge);
+    gr.ntiles = p.ntiles;
+    return gr;
+}
+
 // Pinned host words the level loop reads the frontier counters into.
 static unsigned long long *pinned_counters()
 {
@@ -208,32 +297,34 @@ static unsigned long long *pinned_counters()
     return buf;
 }
 
+#define PROF(kind, st, call)          \
+    [&]() {                           \
+        void *tok__;                  \
+        prof_begin(kind, st, &tok__); \
+        hipError_t e__ = (call);      \
+        prof_end(tok__);              \
+        return e__;                   \
+    }()
+
 static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_batch *b, uint32_t *dist,
                                  uint64_t *masks, int32_t *status, char *ws, hipStream_t st)
 {
-    GraphArgs gr{};
-    gr.n = p.n;
-    gr.m = p.m;
-    gr.row_ptr = g->row_ptr;
-    gr.col = g->col;
-    gr.tile_row = (const int32_t *)(ws + p.off_tiles_row);
-    gr.tile_edge = (const int32_t *)(ws + p.off_tiles_edge);
-    gr.ntiles = p.ntiles;
+    const GraphArgs gr = graph_args(p, g, ws);
     const int32_t *d_cptr = (const int32_t *)(ws + p.off_cptr);
     const int32_t *d_src = (const int32_t *)(ws + p.off_src);
     OutArgs o{dist, masks, status, p.R};
     unsigned long long *hc = pinned_counters();
     if (!hc) return fail(CBFS_E_NOMEM, "cbfs_run_batch: pinned host counters");
     hipError_t e;
-    if ((e = launch_tiles(g->row_ptr, p.n, p.m, p.ntiles, (int32_t *)(ws + p.off_tiles_row),
-                          (int32_t *)(ws + p.off_tiles_edge), st)) != hipSuccess)
-        return hip_fail("tiles", e);
+    cbfs_run_stats &rs = g_last.host;
     const SlotArgs s = slot_at(p, ws, 0);
     const int64_t max_rounds = p.n + 2 * (int64_t)p.R + 4;
     for (int32_t grp = 0; grp < p.groups; grp++) {
         const GroupDesc gd = group_desc(p, b, grp);
-        if ((e = launch_init(p.W, s, p.n, gd, o, st)) != hipSuccess) return hip_fail("init", e);
-        if ((e = launch_seed(p.W, p.WC, s, gr, gd, d_src, d_cptr, st)) != hipSuccess) return hip_fail("seed", e);
+        if ((e = PROF(CBFS_KERNEL_INIT, st, launch_init(p.W, s, p.n, gd, o, st))) != hipSuccess)
+            return hip_fail("init", e);
+        if ((e = PROF(CBFS_KERNEL_SEED, st, launch_seed(p.W, p.WC, s, gr, gd, d_src, d_cptr, st))) != hipSuccess)
+            return hip_fail("seed", e);
         bool dense = false;
         for (int32_t round = 0;; round++) {
             if (round > max_rounds) return fail(CBFS_E_HIP, "cbfs_run_batch: level loop did not terminate");
@@ -250,12 +341,58 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
             else if (p.alpha < 0) dense = false;
             else if (!dense) dense = (double)(verts + degsum) > (double)p.m / p.alpha;
             else dense = (double)verts > (double)p.n / p.beta;
-            if (dense) e = launch_pull(p.W, p.WC, s, gr, gd, o, round, pieces, st);
-            else e = launch_push(p.W, p.WC, s, gr, gd, o, round, pieces, st);
+            rs.rounds++;
+            (dense ? rs.pull_rounds : rs.push_rounds)++;
+            rs.frontier_vertices += verts;
+            rs.frontier_arcs += degsum;
+            if (dense) e = PROF(CBFS_KERNEL_PULL, st, launch_pull(p.W, p.WC, s, gr, gd, o, round, st));
+            else e = PROF(CBFS_KERNEL_PUSH, st, launch_push(p.W, p.WC, s, gr, gd, o, round, pieces, st));
             if (e != hipSuccess) return hip_fail(dense ? "pull" : "push", e);
         }
-        if ((e = launch_finalize(p.W, p.WC, s, p.n, gd, o, st)) != hipSuccess) return hip_fail("finalize", e);
+        if ((e = PROF(CBFS_KERNEL_FINALIZE, st, launch_finalize(p.W, p.WC, s, p.n, gd, o, st))) != hipSuccess)
+            return hip_fail("finalize", e);
     }
+    return CBFS_OK;
+}
+
+static cbfs_status run_persistent(const Plan &p, const cbfs_csr *g, uint32_t *dist, uint64_t *masks,
+                                  int32_t *status, char *ws, hipStream_t st)
+{
+    int blocks = 0;
+    hipError_t e;
+    if ((e = persistent_grid(p.W, p.WC, p.blocks_per_cu, &blocks)) != hipSuccess)
+        return hip_fail("persistent occupancy", e);
+    g_last.host.persistent_blocks = blocks;
+    if (p.slots > blocks) return fail(CBFS_E_ARG, "cbfs_run_batch: more group slots than resident blocks");
+    PersistArgs a{};
+    a.gr = graph_args(p, g, ws);
+    a.o = OutArgs{dist, masks, status, p.R};
+    a.slots = (const SlotArgs *)(ws + p.off_slotdesc);
+    a.groups = (const GroupDesc *)(ws + p.off_groupdesc);
+    a.num_groups = p.groups;
+    a.num_slots = p.slots;
+    a.sources = (const int32_t *)(ws + p.off_src);
+    a.cluster_ptr = (const int32_t *)(ws + p.off_cptr);
+    a.bar = (unsigned int *)(ws + p.off_ctl);
+    a.err = (int32_t *)(ws + p.off_ctl + 16);
+    a.work = (unsigned long long *)(ws + p.off_ctl + 64);
+    a.stats = (long long *)(ws + p.off_stats);
+    a.alpha = p.alpha;
+    a.beta = p.beta;
+    a.force_pull = p.force_pull;
+    a.schedule = p.schedule;
+    a.max_rounds = p.n + 2 * (int64_t)p.R + 4;
+    // barrier, error flag and statistics start at zero (plain memsets: this
+    // path is never captured into a graph)
+    if ((e = hipMemsetAsync(ws + p.off_ctl, 0, 64 + sizeof(unsigned long long) * 3, st)) != hipSuccess)
+        return hip_fail("control reset", e);
+    if ((e = hipMemsetAsync(ws + p.off_stats, 0, sizeof(long long) * 5 * (size_t)p.groups, st)) != hipSuccess)
+        return hip_fail("stats reset", e);
+    if ((e = PROF(CBFS_KERNEL_PERSISTENT, st, launch_persistent(p.W, p.WC, a, blocks, st))) != hipSuccess)
+        return hip_fail("persistent launch", e);
+    g_last.device_stats = true;
+    g_last.stats = a.stats;
+    g_last.err = a.err;
     return CBFS_OK;
 }
 
@@ -301,14 +438,101 @@ extern "C" cbfs_status cbfs_run_batch(const cbfs_csr *g, const cbfs_batch *b, co
     if (workspace_bytes < p.total) return fail(CBFS_E_WORKSPACE, "cbfs_run_batch: workspace too small");
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)workspace;
+    g_last = LastRun{};
+    g_last.valid = true;
+    g_last.stream = st;
+    g_last.host.groups = p.groups;
+    g_last.host.group_words = p.W;
+    g_last.host.slots = p.slots;
+    g_last.host.mode = p.mode;
+
+    // one upload of the batch tables, then the host arrays are released
+    std::vector<char> stage(p.off_slots, 0);
+    std::memcpy(stage.data() + p.off_cptr, b->cluster_ptr, sizeof(int32_t) * (size_t)(p.C + 1));
+    std::memcpy(stage.data() + p.off_src, b->sources, sizeof(int32_t) * (size_t)p.total_sources);
+    for (int32_t sl = 0; sl < p.slots; sl++) {
+        SlotArgs s = slot_at(p, ws, sl);
+        std::memcpy(stage.data() + p.off_slotdesc + sizeof(SlotArgs) * sl, &s, sizeof(SlotArgs));
+    }
+    for (int32_t grp = 0; grp < p.groups; grp++) {
+        GroupDesc d = group_desc(p, b, grp);
+        std::memcpy(stage.data() + p.off_groupdesc + sizeof(GroupDesc) * grp, &d, sizeof(GroupDesc));
+    }
     hipError_t e;
-    if ((e = hipMemcpyAsync(ws + p.off_cptr, b->cluster_ptr, sizeof(int32_t) * (size_t)(p.C + 1),
-                            hipMemcpyHostToDevice, st)) != hipSuccess)
-        return hip_fail("cluster_ptr upload", e);
-    if ((e = hipMemcpyAsync(ws + p.off_src, b->sources, sizeof(int32_t) * (size_t)p.total_sources,
-                            hipMemcpyHostToDevice, st)) != hipSuccess)
-        return hip_fail("sources upload", e);
-    // the host arrays belong to the caller once we return
+    const size_t lo = p.off_cptr, hi = p.off_ctl;
+    if ((e = hipMemcpyAsync(ws + lo, stage.data() + lo, hi - lo, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_fail("batch upload", e);
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail("upload sync", e);
-    return run_host_loop(p, g, b, dist, masks, cluster_status, ws, st);
+    if ((e = PROF(CBFS_KERNEL_TILES, st,
+                  launch_tiles(g->row_ptr, p.n, p.m, p.ntiles, (int32_t *)(ws + p.off_tiles_row),
+                               (int32_t *)(ws + p.off_tiles_edge), st))) != hipSuccess)
+        return hip_fail("tiles", e);
+    if (p.mode == CBFS_MODE_HOST_LOOP) return run_host_loop(p, g, b, dist, masks, cluster_status, ws, st);
+    return run_persistent(p, g, dist, masks, cluster_status, ws, st);
+}
+
+extern "C" cbfs_status cbfs_last_run_stats(cbfs_run_stats *out)
+{
+    if (!out) return fail(CBFS_E_ARG, "cbfs_last_run_stats: null output");
+    if (!g_last.valid) return fail(CBFS_E_ARG, "cbfs_last_run_stats: no cbfs_run_batch call on this thread");
+    cbfs_run_stats r = g_last.host;
+    if (g_last.device_stats) {
+        std::vector<long long> st(5 * (size_t)r.groups);
+        int32_t err = 0;
+        hipError_t e;
+        if ((e = hipStreamSynchronize(g_last.stream)) != hipSuccess) return hip_fail("stats sync", e);
+        if ((e = hipMemcpy(st.data(), g_last.stats, sizeof(long long) * st.size(), hipMemcpyDeviceToHost)) !=
+            hipSuccess)
+            return hip_fail("stats copy", e);
+        if ((e = hipMemcpy(&err, g_last.err, sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail("error flag copy", e);
+        for (int64_t grp = 0; grp < r.groups; grp++) {
+            r.rounds += st[5 * grp + 0];
+            r.push_rounds += st[5 * grp + 1];
+            r.pull_rounds += st[5 * grp + 2];
+            r.frontier_vertices += st[5 * grp + 3];
+            r.frontier_arcs += st[5 * grp + 4];
+        }
+        r.device_error = err;
+    }
+    *out = r;
+    if (r.device_error == 1) return fail(CBFS_E_HIP, "persistent kernel: grid barrier timed out");
+    if (r.device_error == 2) return fail(CBFS_E_HIP, "persistent kernel: level loop did not terminate");
+    return CBFS_OK;
+}
+
+extern "C" cbfs_status cbfs_profile_enable(int32_t enable)
+{
+    for (auto &r : g_prof) {
+        hipEventDestroy(r.start);
+        hipEventDestroy(r.stop);
+    }
+    g_prof.clear();
+    for (int k = 0; k < CBFS_KERNEL_KINDS; k++) {
+        g_prof_launches[k] = 0;
+        g_prof_ms[k] = 0.0;
+    }
+    g_prof_on = enable != 0;
+    return CBFS_OK;
+}
+
+extern "C" cbfs_status cbfs_profile_read(int64_t *launches, double *total_ms)
+{
+    if (!launches || !total_ms) return fail(CBFS_E_ARG, "cbfs_profile_read: null output");
+    for (auto &r : g_prof) {
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e != hipSuccess) return hip_fail("profile event sync", e);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, r.start, r.stop);
+        g_prof_launches[r.kind]++;
+        g_prof_ms[r.kind] += ms;
+        hipEventDestroy(r.start);
+        hipEventDestroy(r.stop);
+    }
+    g_prof.clear();
+    for (int k = 0; k < CBFS_KERNEL_KINDS; k++) {
+        launches[k] = g_prof_launches[k];
+        total_ms[k] = g_prof_ms[k];
+    }
+    return CBFS_OK;
 }

@@ -73,12 +73,12 @@ def _clib():
 
 
 def build(force: bool = True) -> str:
-    """Compile ``synth/synth.c`` with gcc (C + OpenMP)."""
+    """Compile ``synth/synth.c`` with gcc (C + pthreads)."""
     src = os.path.join(_HERE, "synth.c")
     so = os.path.join(_HERE, "libsynth.so")
     if force or not os.path.exists(so):
         tmp = so + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-pthread", "-fPIC", "-shared", "-Wall",
                                "-o", tmp, src])
         os.replace(tmp, so)
     return so

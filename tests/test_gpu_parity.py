@@ -61,7 +61,11 @@ def assert_same(gpu, ref, where=""):
             raise AssertionError(f"{where} masks of cluster {c} differ at {bad[:5].tolist()}")
 
 
-TUNINGS = [None, dict(alpha=-1.0), dict(force_pull=1), dict(group_words=1), dict(group_words=8, alpha=5.0)]
+TUNINGS = [None, dict(alpha=-1.0), dict(force_pull=1), dict(group_words=1), dict(group_words=8, alpha=5.0),
+           dict(mode=1), dict(mode=1, force_pull=1, group_words=2), dict(mode=1, alpha=-1.0),
+           dict(mode=2, concurrent_groups=3, group_words=1), dict(mode=2, concurrent_groups=64, group_words=1,
+                                                                   alpha=-1.0)]
+TUNING_IDS = ["default", "push", "pull", "w1", "w8", "host", "host_pull_w2", "host_push", "slots3", "slots64"]
 
 
 def tuning_of(t, WC=1):
@@ -69,7 +73,7 @@ def tuning_of(t, WC=1):
     if t is None:
         return None
     t = dict(t)
-    if "group_words" in t and t["group_words"] % WC:
+    if "group_words" in t and (t["group_words"] % WC or (WC == 3 and t["group_words"] != 3)):
         t["group_words"] = WC
     return P.Tuning(**t)
 
@@ -88,7 +92,7 @@ def small_cases():
 
 
 @pytest.mark.parametrize("name,gen,R,k", small_cases(), ids=[c[0] for c in small_cases()])
-@pytest.mark.parametrize("tun", TUNINGS, ids=["default", "push", "pull", "w1", "w8"])
+@pytest.mark.parametrize("tun", TUNINGS, ids=TUNING_IDS)
 def test_parity_small(name, gen, R, k, tun):
     n, s, d = gen()
     hops = R
@@ -154,10 +158,14 @@ def workload_inputs(name):
 
 
 @pytest.mark.parametrize("name", ["rmat12_small", "rmat16_batch", "grid128_small", "chunglu16_small", "rmat14"])
-def test_parity_workloads_small(name):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_parity_workloads_small(name, mode):
+    import paper_2410_17226_amd as P
     cfg, (ours, ref_in) = workload_inputs(name)
     rp, col, cp, src = ours
-    gpu = gpu_cbfs(rp, col, cp, src, cfg["R"])
+    gpu = gpu_cbfs(rp, col, cp, src, cfg["R"], P.Tuning(mode=mode))
     ref = oracle.cbfs(*ref_in, R=cfg["R"])
     assert_same(gpu, ref, name)
     assert (ref[2] == 0).all()
+    stats = P.last_run_stats()
+    assert stats["device_error"] == 0 and stats["rounds"] > 0

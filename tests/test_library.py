@@ -125,6 +125,8 @@ def test_run_batch_argument_errors_before_launch():
     # bad tuning
     assert _call_run_batch(100, 400, [0, 2], [1, 2], 1, tuning=P.Tuning(group_words=3)) == -1
     assert _call_run_batch(100, 400, [0, 2], [1, 2], 1, tuning=P.Tuning(block_size=128)) == -1
+    assert _call_run_batch(100, 400, [0, 2], [1, 2], 1, tuning=P.Tuning(concurrent_groups=65)) == -1
+    assert _call_run_batch(100, 400, [0, 2], [1, 2], 1, tuning=P.Tuning(mode=3)) == -1
 
 
 def test_workspace_size_monotone():
@@ -137,5 +139,10 @@ def test_workspace_size_monotone():
     s1 = size(1000, 5000, 64, 4)
     assert s1 > 3 * 1000 * 8
     assert size(2000, 5000, 64, 4) > s1
-    assert size(1000, 5000, 64, 4, P.Tuning(group_words=8)) >= size(1000, 5000, 64, 4, P.Tuning(group_words=1))
+    one = dict(concurrent_groups=1)
+    assert size(1000, 5000, 64, 4, P.Tuning(group_words=8, **one)) >= size(1000, 5000, 64, 4,
+                                                                           P.Tuning(group_words=1, **one))
+    # side-by-side group slots each carry their own search state
+    assert size(1000, 5000, 64, 4, P.Tuning(group_words=1, concurrent_groups=4)) > \
+        size(1000, 5000, 64, 4, P.Tuning(group_words=1, **one))
     assert size(1000, 5000, 300, 1) == 0  # invalid: more than 256 sources

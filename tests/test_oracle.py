@@ -232,7 +232,7 @@ def test_multiword_cluster():
 def test_radius_violation_and_unreachable():
     # path 0-1-2-3 plus a separate edge 4-5
     rp, col = csr_of(6, [(0, 1), (1, 2), (2, 3), (4, 5)])
-    dist, masks, st = oracle.cbfs(rp, col, [0, 2, 4, 6], [1, 3, 1, 0], R=1)
+    dist, masks, st = oracle.cbfs(rp, col, [0, 2, 4], [1, 3, 1, 0], R=1)
     assert st[0] == oracle.E_RADIUS       # source 3 is two hops from center 1
     assert st[1] == 0
     assert dist[1, 4] == U32MAX and dist[1, 5] == U32MAX
