@@ -174,8 +174,9 @@ typedef struct {
     int32_t force_pull;        /* 1: pull every round (testing)                         */
     int32_t blocks_per_cu;     /* persistent mode: resident blocks per compute unit;
                                   0 = as many as fit                                    */
-    int32_t schedule;          /* persistent mode: 0 = blocks take work items from a
-                                  shared counter, 1 = fixed stride over the items       */
+    int32_t schedule;          /* persistent mode: 0 = fixed stride over the items
+                                  (default), 1 = blocks take work items from a shared
+                                  counter                                               */
     int32_t reserved;
 } cbfs_tuning;
 

@@ -9,12 +9,16 @@
 //   seen   [n][W]  Seen_{i-1}(v): lets the vertex phase form the new bits
 //                  Seen_i \ Seen_{i-1} while other threads already OR round-i
 //                  contributions into nxt.
-//   queue  2 x [cap] int64 frontier entries (piece << 32 | vertex); a vertex of
+//   queue  3 x [cap] int64 frontier entries (piece << 32 | vertex); a vertex of
 //                  degree deg occupies max(1, ceil(deg / PIECE)) pieces so that
-//                  no work item carries more than PIECE arcs.
+//                  no work item carries more than PIECE arcs.  Round i reads
+//                  queue[i%3] (F_i), fills queue[(i+1)%3] and may use
+//                  queue[(i+2)%3] (F_{i-1}) to clear F_{i-1}'s bitmap words.
 //   bits   3 x [ceil(n/64)] frontier membership bitmaps; round i reads bits[i%3],
-//                  fills bits[(i+1)%3] and clears bits[(i+2)%3].
-//   ctr    3 x 4 counters per rotation: pieces, vertices, degree sum, spare.
+//                  fills bits[(i+1)%3] and clears bits[(i+2)%3] (F_{i-1}).
+//   ctr    4 x 4 counters per rotation: pieces, vertices, degree sum, spare.
+//                  Round i reads ctr[i%4] and ctr[(i-1)%4], fills ctr[(i+1)%4]
+//                  and clears ctr[(i+2)%4].
 //
 // Invariant (Algorithm "Cluster-BFS search from S", Section 3.2): after the
 // vertex phase of round i, Seen_i(u) = {s : d(s,u) <= i}; the edge phase makes
@@ -52,9 +56,9 @@ struct GraphArgs {
 
 struct SlotArgs {
     uint64_t *A, *B, *seen;
-    int64_t *q0, *q1;
+    int64_t *q0, *q1, *q2;
     uint64_t *bits0, *bits1, *bits2;
-    unsigned long long *ctr;  // [3][4]
+    unsigned long long *ctr;  // [4][4]
     int64_t nwords;           // bitmap words
 };
 
@@ -73,12 +77,16 @@ struct OutArgs {
 
 __device__ __forceinline__ uint64_t *cur_buf(const SlotArgs &s, int round) { return (round & 1) ? s.B : s.A; }
 __device__ __forceinline__ uint64_t *nxt_buf(const SlotArgs &s, int round) { return (round & 1) ? s.A : s.B; }
-__device__ __forceinline__ int64_t *q_buf(const SlotArgs &s, int round) { return (round & 1) ? s.q1 : s.q0; }
+__device__ __forceinline__ int64_t *q_buf(const SlotArgs &s, int round)
+{
+    const int r = round % 3;
+    return r == 0 ? s.q0 : (r == 1 ? s.q1 : s.q2);
+}
 __device__ __forceinline__ uint64_t *bits_buf(const SlotArgs &s, int r3)
 {
     return r3 == 0 ? s.bits0 : (r3 == 1 ? s.bits1 : s.bits2);
 }
-__device__ __forceinline__ unsigned long long *ctr_buf(const SlotArgs &s, int round) { return s.ctr + 4 * (round % 3); }
+__device__ __forceinline__ unsigned long long *ctr_buf(const SlotArgs &s, int round) { return s.ctr + 4 * (round & 3); }
 
 __device__ __forceinline__ unsigned long long or64(uint64_t *p, uint64_t v)
 {

@@ -11,6 +11,13 @@ namespace cbfs {
 
 constexpr int MAX_SLOTS = 64;  // group slots searched side by side in one persistent launch
 constexpr int GRAB = 4;        // work items a persistent block takes per counter update
+constexpr int DIES = 8;        // accelerator dies (XCDs), each with its own L2
+// Barrier control words, one 128-byte line each: generation, die-leader
+// arrivals, then per die: arrivals, registered blocks, die generation.
+constexpr int CTL_LINE = 32;   // words per line
+constexpr int CTL_GEN = 0, CTL_COUNT = 1, CTL_DIE_COUNT = 2, CTL_DIE_TOTAL = 2 + DIES,
+              CTL_DIE_GEN = 2 + 2 * DIES;
+constexpr int CTL_WORDS = CTL_LINE * (2 + 3 * DIES);
 
 // Arguments of the persistent batch kernel (all pointers are device memory).
 struct PersistArgs {
@@ -21,13 +28,13 @@ struct PersistArgs {
     int32_t num_groups, num_slots;
     const int32_t *sources;     // batch sources
     const int32_t *cluster_ptr; // batch cluster_ptr
-    unsigned int *bar;          // [2] grid barrier: arrivals, generation
+    unsigned int *ctl;          // [CTL_WORDS] barrier state, work counters (zeroed before launch)
     unsigned long long *work;   // [3] per-round work counters
     int32_t *err;               // 0 ok, 1 barrier timeout, 2 round limit
     long long *stats;           // [num_groups][5]: rounds, push, pull, sum |F|, sum deg(F)
     float alpha, beta;
     int32_t force_pull;
-    int32_t schedule;           // 0 shared work counter, 1 fixed stride
+    int32_t schedule;           // 0 fixed stride, 1 shared work counter
     int64_t max_rounds;
 };
 

@@ -81,35 +81,111 @@ __global__ void k_finalize(SlotArgs s, int64_t n, GroupDesc g, OutArgs o)
 // Persistent batch kernel.
 // ---------------------------------------------------------------------------
 
-// Grid barrier (arrival counter + generation) for a cooperative launch, where
-// every block is resident.  The wait is bounded: past the spin limit the block
+// Grid barrier for a cooperative launch, where every block is resident.
+//
+// Memory ordering across the dies: each die has its own L2, so an agent-scope
+// release writes the die's dirty L2 lines back and an agent-scope acquire
+// invalidates the die's L2.  The barrier has two levels so that this happens
+// once per die, not once per block:
+//   - every block waits for its own stores to reach L2, then counts itself in
+//     on its die;
+//   - the last block of a die (the die leader) writes the die's L2 back and
+//     counts the die in globally; the last die bumps the generation;
+//   - each die leader, seeing the new generation, invalidates its die's L2 and
+//     then opens its die; the other blocks of the die, seeing the die open,
+//     take their own acquire (their compute unit's L1).
+// Arrivals and polls are relaxed atomics, performed coherently without
+// touching cached data.  The waits are bounded: after BARRIER_TIMEOUT_TICKS of
+// the constant-rate wall clock (or once another block has aborted) a block
 // raises the abort flag, and every block leaves its loops at the next check,
 // so the grid always drains.
-__device__ __forceinline__ bool grid_barrier(unsigned int *bar, unsigned int nblocks, int32_t *abort_flag)
+constexpr unsigned long long BARRIER_TIMEOUT_TICKS = 400000000ull;  // 4 s at 100 MHz
+
+__device__ __forceinline__ unsigned int ld_relaxed(const unsigned int *p)
 {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait until *p != old (thread 0 only).  Returns false on timeout/abort.
+__device__ __forceinline__ bool wait_change(const unsigned int *p, unsigned int old, int32_t *abort_flag)
+{
+    const unsigned long long t0 = wall_clock64();
+    unsigned int naps = 1;
+    while (ld_relaxed(p) == old) {
+        for (unsigned int k = 0; k < naps; k++) __builtin_amdgcn_s_sleep(4);
+        if (naps < 16) naps <<= 1;
+        if (wall_clock64() - t0 > BARRIER_TIMEOUT_TICKS ||
+            __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+    return true;
+}
+
+__device__ __forceinline__ unsigned int die_id()
+{
+    return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & (DIES - 1);  // HW_REG_XCC_ID[3:0]
+}
+
+// Flat barrier over all blocks, used once to register the blocks of each die.
+__device__ bool flat_barrier(unsigned int *ctl, unsigned int nblocks, int32_t *abort_flag, int32_t &s_abort)
+{
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned int *count = bar, *gen = bar + 1;
-        const unsigned int g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const unsigned int arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
+        unsigned int *gen = ctl + CTL_LINE * CTL_GEN, *count = ctl + CTL_LINE * CTL_COUNT;
+        const unsigned int g = ld_relaxed(gen);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nblocks - 1) {
             __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            long long spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > (1ll << 28)) {
-                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-            }
+            wait_change(gen, g, abort_flag);
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_abort = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     }
     __syncthreads();
-    return __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    return s_abort != 0;
+}
+
+__device__ __forceinline__ bool grid_barrier(unsigned int *ctl, unsigned int die, unsigned int ndies,
+                                             int32_t *abort_flag, int32_t &s_abort)
+{
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int *gen = ctl + CTL_LINE * CTL_GEN, *count = ctl + CTL_LINE * CTL_COUNT;
+        unsigned int *dcount = ctl + CTL_LINE * (CTL_DIE_COUNT + die);
+        unsigned int *dgen = ctl + CTL_LINE * (CTL_DIE_GEN + die);
+        const unsigned int dtotal = ld_relaxed(ctl + CTL_LINE * (CTL_DIE_TOTAL + die));
+        const unsigned int dg = ld_relaxed(dgen);
+        const unsigned int g = ld_relaxed(gen);
+        if (__hip_atomic_fetch_add(dcount, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == dtotal - 1) {
+            // die leader: every block of the die has arrived
+            __hip_atomic_store(dcount, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ndies - 1) {
+                __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                wait_change(gen, g, abort_flag);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the die's L2 and this L1
+            __builtin_amdgcn_s_waitcnt(0);
+            __hip_atomic_fetch_add(dgen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            wait_change(dgen, dg, abort_flag);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        // one read of the flag for the whole block, so every wave takes the same exit
+        s_abort = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    }
+    __syncthreads();
+    return s_abort != 0;
 }
 
 __device__ __forceinline__ unsigned long long ld_ctr(const unsigned long long *p)
@@ -118,14 +194,17 @@ __device__ __forceinline__ unsigned long long ld_ctr(const unsigned long long *p
 }
 
 // Block-uniform: copy slot `sl`'s descriptors into LDS, where the global
-// stores of the round cannot alias them.
+// stores of the round cannot alias them, and record which slot they hold.
+// Every write of these LDS words happens here, between two barriers, so every
+// wave reads the same values afterwards.
 __device__ __forceinline__ void load_desc(const PersistArgs &a, int32_t wave0, int32_t sl, SlotArgs &s_slot,
-                                          GroupDesc &s_group)
+                                          GroupDesc &s_group, int32_t &s_cached)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
         s_slot = a.slots[sl];
         s_group = a.groups[wave0 + sl];
+        s_cached = sl;
     }
     __syncthreads();
 }
@@ -135,87 +214,137 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
 {
     __shared__ RoundSmem<W> sm;
     __shared__ int32_t s_dense[MAX_SLOTS];
+    __shared__ int32_t s_done[MAX_SLOTS];   // frontier emptied: the slot's counters are no longer maintained
+    __shared__ int32_t s_sparse[MAX_SLOTS];
+    __shared__ int64_t s_work[MAX_SLOTS];   // push chunks or pull tiles
+    __shared__ int64_t s_nq[MAX_SLOTS];     // pieces in F_i
+    __shared__ int64_t s_nprev[MAX_SLOTS];  // pieces in F_{i-1}
     __shared__ int64_t s_pref[MAX_SLOTS + 1];
-    __shared__ int64_t s_nq[MAX_SLOTS];
+    __shared__ int tmp[WAVES + 1];
     __shared__ int32_t s_stop;
     __shared__ int64_t s_grab;
     __shared__ SlotArgs s_slot;
     __shared__ GroupDesc s_group;
     __shared__ int32_t s_cached;
+    __shared__ int32_t s_abort;
+
+    __shared__ uint32_t s_ndies;
 
     const unsigned int nb = gridDim.x;
     const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int64_t gstride = (int64_t)nb * BLOCK;
     const int32_t S = a.num_slots;
-    bool aborted = false;
+    const unsigned int die = die_id();
+
+    // register this block on its die, then learn how many dies have blocks
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(a.ctl + CTL_LINE * (CTL_DIE_TOTAL + die), 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    bool aborted = flat_barrier(a.ctl, nb, a.err, s_abort);
+    if (threadIdx.x == 0) {
+        uint32_t k = 0;
+        for (int d = 0; d < DIES; d++) k += ld_relaxed(a.ctl + CTL_LINE * (CTL_DIE_TOTAL + d)) > 0 ? 1 : 0;
+        s_ndies = k;
+    }
+    __syncthreads();
+    const unsigned int ndies = s_ndies;
 
     for (int32_t wave0 = 0; wave0 < a.num_groups && !aborted; wave0 += S) {
         const int32_t active = a.num_groups - wave0 < S ? a.num_groups - wave0 : S;
         for (int32_t sl = 0; sl < active; sl++) {
-            load_desc(a, wave0, sl, s_slot, s_group);
+            load_desc(a, wave0, sl, s_slot, s_group, s_cached);
             init_part<W>(s_slot, a.gr.n, s_group, a.o, gtid, gstride);
         }
         if (gtid < 3) a.work[gtid] = 0;
-        if ((aborted = grid_barrier(a.bar, nb, a.err))) break;
+        if ((aborted = grid_barrier(a.ctl, die, ndies, a.err, s_abort))) break;
         for (int32_t sl = blockIdx.x; sl < active; sl += nb) {
-            load_desc(a, wave0, sl, s_slot, s_group);
+            load_desc(a, wave0, sl, s_slot, s_group, s_cached);
             seed_block<W, WC>(sm.push.st, s_slot, a.gr, s_group, a.sources, a.cluster_ptr);
         }
-        if (threadIdx.x < MAX_SLOTS) s_dense[threadIdx.x] = a.force_pull ? 1 : 0;
-        if ((aborted = grid_barrier(a.bar, nb, a.err))) break;
+        if (threadIdx.x < MAX_SLOTS) {
+            s_dense[threadIdx.x] = a.force_pull ? 1 : 0;
+            s_done[threadIdx.x] = 0;
+        }
+        if ((aborted = grid_barrier(a.ctl, die, ndies, a.err, s_abort))) break;
 
         for (int32_t round = 0;; round++) {
-            // every block takes the same decisions from the same counters
-            if (threadIdx.x == 0) {
-                int64_t acc = 0;
-                for (int32_t sl = 0; sl < active; sl++) {
-                    const unsigned long long *c = ctr_buf(a.slots[sl], round);
-                    const int64_t pieces = (int64_t)ld_ctr(c + 0), verts = (int64_t)ld_ctr(c + 1),
-                                  degsum = (int64_t)ld_ctr(c + 2);
-                    int64_t items = 0;
-                    if (verts > 0) {
-                        // direction choice (Appendix A, Algorithm "EdgeMap")
-                        int32_t dense = s_dense[sl];
-                        if (a.force_pull) dense = 1;
-                        else if (a.alpha < 0.f) dense = 0;
-                        else if (!dense) dense = (double)(verts + degsum) > (double)a.gr.m / a.alpha;
-                        else dense = (double)verts > (double)a.gr.n / a.beta;
-                        s_dense[sl] = dense;
-                        items = dense ? a.gr.ntiles : (pieces + BLOCK - 1) / BLOCK;
-                        if (blockIdx.x == 0) {
-                            long long *st = a.stats + 5 * (int64_t)(wave0 + sl);
-                            st[0] += 1;
-                            st[dense ? 2 : 1] += 1;
-                            st[3] += verts;
-                            st[4] += degsum;
-                        }
+            // Decision: thread sl reads slot sl's counters (F_i and F_{i-1});
+            // every block takes the same decisions from the same values.
+            int64_t items = 0, work = 0;
+            const int32_t sl_me = threadIdx.x;
+            if (sl_me < active && !s_done[sl_me]) {
+                const SlotArgs &sd = a.slots[sl_me];
+                const unsigned long long *c = ctr_buf(sd, round);
+                const int64_t pieces = (int64_t)ld_ctr(c + 0), verts = (int64_t)ld_ctr(c + 1),
+                              degsum = (int64_t)ld_ctr(c + 2);
+                const int64_t nprev = round > 0 ? (int64_t)ld_ctr(ctr_buf(sd, round - 1) + 0) : 0;
+                if (verts > 0) {
+                    // direction choice (Appendix A, Algorithm "EdgeMap")
+                    int32_t dense = s_dense[sl_me];
+                    if (a.force_pull) dense = 1;
+                    else if (a.alpha < 0.f) dense = 0;
+                    else if (!dense) dense = (double)(verts + degsum) > (double)a.gr.m / a.alpha;
+                    else dense = (double)verts > (double)a.gr.n / a.beta;
+                    s_dense[sl_me] = dense;
+                    work = dense ? a.gr.ntiles : (pieces + BLOCK - 1) / BLOCK;
+                    // bitmap words of F_{i-1} to clear: sparse through its queue
+                    // when that is cheaper than a dense pass
+                    const bool sparse = nprev * 4 < sd.nwords;
+                    s_sparse[sl_me] = sparse;
+                    const int64_t clears = round == 0 ? 0
+                                           : (sparse ? (nprev + BLOCK - 1) / BLOCK
+                                                     : (sd.nwords + CLEAR_WORDS - 1) / CLEAR_WORDS);
+                    items = work + clears;
+                    if (blockIdx.x == 0) {
+                        long long *st = a.stats + 5 * (int64_t)(wave0 + sl_me);
+                        st[0] += 1;
+                        st[dense ? 2 : 1] += 1;
+                        st[3] += verts;
+                        st[4] += degsum;
                     }
-                    s_nq[sl] = pieces;
-                    s_pref[sl] = acc;
-                    acc += items;
                 }
-                s_pref[active] = acc;
-                s_cached = -1;
-                s_stop = acc == 0 ? 1 : (round > a.max_rounds ? 2 : 0);
-                if (s_stop == 2 && blockIdx.x == 0)
-                    __hip_atomic_store(a.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (verts == 0) s_done[sl_me] = 1;
+                s_work[sl_me] = work;
+                s_nq[sl_me] = pieces;
+                s_nprev[sl_me] = nprev;
+            } else if (sl_me < active) {
+                s_work[sl_me] = 0;
+            }
+            // items of the slots, in slot order (active <= MAX_SLOTS <= BLOCK)
+            int total_work;
+            const int wpos = block_exclusive_scan(work > 0 ? 1 : 0, tmp, &total_work);
+            (void)wpos;
+            {
+                // 64-bit prefix of the item counts over the first `active` threads
+                const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+                int64_t v = items;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int64_t y = __shfl_up(v, d, 64);
+                    if (lane >= d) v += y;
+                }
+                // MAX_SLOTS <= 64: the slots all sit in wave 0
+                if (wid == 0 && threadIdx.x < active) s_pref[threadIdx.x + 1] = v;
+                if (threadIdx.x == 0) {
+                    s_pref[0] = 0;
+                    s_stop = total_work == 0 ? 1 : (round > a.max_rounds ? 2 : 0);
+                    if (s_stop == 2 && blockIdx.x == 0)
+                        __hip_atomic_store(a.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
             __syncthreads();
             if (s_stop) break;
-            for (int32_t sl = 0; sl < active; sl++) {
-                load_desc(a, wave0, sl, s_slot, s_group);
-                clear_ahead_part(s_slot, round, gtid, gstride);
-            }
-            if (threadIdx.x == 0) s_cached = active > 0 ? active - 1 : -1;
             // the work counter of round i+2 last served round i-1
             if (blockIdx.x == 0 && threadIdx.x == 0) a.work[(round + 2) % 3] = 0;
-            // blocks take GRAB items at a time from the round's counter
+            // blocks take GRAB items at a time from the round's counter (or a
+            // fixed stride), items being slot-major: push chunks or pull tiles,
+            // then bitmap clears
             const int64_t total = s_pref[active];
-            unsigned long long *work = a.work + (round % 3);
+            unsigned long long *wctr = a.work + (round % 3);
             int32_t sl = 0;
             for (int64_t next = (int64_t)blockIdx.x * GRAB;; next += (int64_t)nb * GRAB) {
-                if (a.schedule == 0) {
-                    if (threadIdx.x == 0) s_grab = (int64_t)atomicAdd(work, (unsigned long long)GRAB);
+                if (a.schedule == 1) {
+                    if (threadIdx.x == 0) s_grab = (int64_t)atomicAdd(wctr, (unsigned long long)GRAB);
                     __syncthreads();
                     next = s_grab;
                     __syncthreads();
@@ -227,24 +356,25 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                     if (item < s_pref[sl]) sl = 0;
                     while (item >= s_pref[sl + 1]) sl++;
                     const int64_t local = item - s_pref[sl];
-                    // the item's descriptors live in LDS, where the global stores
-                    // of the round cannot alias them
-                    if (sl != s_cached) {
-                        load_desc(a, wave0, sl, s_slot, s_group);
-                        if (threadIdx.x == 0) s_cached = sl;
+                    if (sl != s_cached) load_desc(a, wave0, sl, s_slot, s_group, s_cached);
+                    if (local >= s_work[sl]) {
+                        __syncthreads();
+                        clear_item(s_slot, round, s_sparse[sl] != 0, s_nprev[sl], local - s_work[sl]);
+                    } else if (s_dense[sl]) {
+                        pull_tile<W, WC>(sm.pull, s_slot, a.gr, s_group, a.o, round, (int32_t)local);
+                    } else {
+                        push_chunk<W, WC>(sm.push, s_slot, a.gr, s_group, a.o, round, s_nq[sl], local);
                     }
-                    if (s_dense[sl]) pull_tile<W, WC>(sm.pull, s_slot, a.gr, s_group, a.o, round, (int32_t)local);
-                    else push_chunk<W, WC>(sm.push, s_slot, a.gr, s_group, a.o, round, s_nq[sl], local);
                 }
             }
-            if ((aborted = grid_barrier(a.bar, nb, a.err))) break;
+            if ((aborted = grid_barrier(a.ctl, die, ndies, a.err, s_abort))) break;
         }
         if (aborted) break;
         for (int32_t sl = 0; sl < active; sl++) {
-            load_desc(a, wave0, sl, s_slot, s_group);
+            load_desc(a, wave0, sl, s_slot, s_group, s_cached);
             finalize_part<W, WC>(s_slot, a.gr.n, s_group, a.o, gtid, gstride);
         }
-        if ((aborted = grid_barrier(a.bar, nb, a.err))) break;
+        if ((aborted = grid_barrier(a.ctl, die, ndies, a.err, s_abort))) break;
     }
 }
 

@@ -45,16 +45,40 @@ __device__ __forceinline__ void init_part(const SlotArgs &s, int64_t n, const Gr
         s.bits1[k] = 0;
         s.bits2[k] = 0;
     }
-    if (tid < 12) s.ctr[tid] = 0;
+    if (tid < 16) s.ctr[tid] = 0;
     if (tid < g.nc) o.status[g.c0 + tid] = 0;
 }
 
-// Clear the bitmap and counters of round i+2 (they last served round i-1).
+// Clear the bitmap of F_{i-1} (bits[(i+2)%3]) densely and the counters of
+// round i+2 (they last served round i-2).
 __device__ __forceinline__ void clear_ahead_part(const SlotArgs &s, int32_t round, int64_t tid, int64_t stride)
 {
     uint64_t *clr = bits_buf(s, (round + 2) % 3);
     for (int64_t k = tid; k < s.nwords; k += stride) clr[k] = 0;
     if (tid < 4) ctr_buf(s, round + 2)[tid] = 0;
+}
+
+// One clear item of round i for a slot.  Sparse: zero the bitmap words of the
+// F_{i-1} entries [item*BLOCK, (item+1)*BLOCK) of queue[(i+2)%3] (a word of
+// that bitmap only holds F_{i-1} bits, so the whole word is zeroed).  Dense:
+// zero words [item*CLEAR_WORDS, (item+1)*CLEAR_WORDS) of the bitmap.  Item 0
+// also clears the counters of round i+2.
+constexpr int CLEAR_WORDS = BLOCK * 16;
+
+__device__ __forceinline__ void clear_item(const SlotArgs &s, int32_t round, bool sparse, int64_t nprev, int64_t item)
+{
+    uint64_t *clr = bits_buf(s, (round + 2) % 3);
+    if (sparse) {
+        const int64_t idx = item * BLOCK + threadIdx.x;
+        if (idx < nprev) {
+            const int32_t v = (int32_t)(q_buf(s, round + 2)[idx] & 0xffffffff);
+            clr[v >> 6] = 0;
+        }
+    } else {
+        const int64_t hi = (item + 1) * CLEAR_WORDS < s.nwords ? (item + 1) * CLEAR_WORDS : s.nwords;
+        for (int64_t k = item * CLEAR_WORDS + threadIdx.x; k < hi; k += BLOCK) clr[k] = 0;
+    }
+    if (item == 0 && threadIdx.x < 4) ctr_buf(s, round + 2)[threadIdx.x] = 0;
 }
 
 // Seed (one block): bit i of cluster j at its source s_i, i.e. Seen_0; and

@@ -213,14 +213,14 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
     p.off_src = take(sizeof(int32_t) * (size_t)std::max(1, p.total_sources));
     p.off_slotdesc = take(sizeof(SlotArgs) * MAX_SLOTS);
     p.off_groupdesc = take(sizeof(GroupDesc) * (size_t)p.groups);
-    p.off_ctl = take(64 + sizeof(unsigned long long) * 3);
+    p.off_ctl = take(sizeof(unsigned int) * CTL_WORDS + 256);
     p.off_stats = take(sizeof(long long) * 5 * (size_t)p.groups);
     p.off_slots = off;
     size_t sb = 0;
     sb += 3 * align_up(sizeof(uint64_t) * (size_t)p.n * p.W);
-    sb += 2 * align_up(sizeof(int64_t) * (size_t)p.qcap);
+    sb += 3 * align_up(sizeof(int64_t) * (size_t)p.qcap);
     sb += 3 * align_up(sizeof(uint64_t) * (size_t)p.nwords);
-    sb += align_up(sizeof(unsigned long long) * 12);
+    sb += align_up(sizeof(unsigned long long) * 16);
     p.slot_bytes = sb;
     p.total = off + sb * (size_t)p.slots;
     return CBFS_OK;
@@ -241,6 +241,8 @@ static SlotArgs slot_at(const Plan &p, char *ws, int slot)
     s.q0 = (int64_t *)b;
     b += qb;
     s.q1 = (int64_t *)b;
+    b += qb;
+    s.q2 = (int64_t *)b;
     b += qb;
     size_t bb = align_up(sizeof(uint64_t) * (size_t)p.nwords);
     s.bits0 = (uint64_t *)b;
@@ -328,7 +330,7 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
         bool dense = false;
         for (int32_t round = 0;; round++) {
             if (round > max_rounds) return fail(CBFS_E_HIP, "cbfs_run_batch: level loop did not terminate");
-            if ((e = hipMemcpyAsync(hc, s.ctr + 4 * (round % 3), 3 * sizeof(unsigned long long),
+            if ((e = hipMemcpyAsync(hc, s.ctr + 4 * (round & 3), 3 * sizeof(unsigned long long),
                                     hipMemcpyDeviceToHost, st)) != hipSuccess)
                 return hip_fail("counter copy", e);
             if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail("level sync", e);
@@ -373,9 +375,9 @@ static cbfs_status run_persistent(const Plan &p, const cbfs_csr *g, uint32_t *di
     a.num_slots = p.slots;
     a.sources = (const int32_t *)(ws + p.off_src);
     a.cluster_ptr = (const int32_t *)(ws + p.off_cptr);
-    a.bar = (unsigned int *)(ws + p.off_ctl);
-    a.err = (int32_t *)(ws + p.off_ctl + 16);
-    a.work = (unsigned long long *)(ws + p.off_ctl + 64);
+    a.ctl = (unsigned int *)(ws + p.off_ctl);
+    a.err = (int32_t *)(ws + p.off_ctl + sizeof(unsigned int) * CTL_WORDS);
+    a.work = (unsigned long long *)(ws + p.off_ctl + sizeof(unsigned int) * CTL_WORDS + 128);
     a.stats = (long long *)(ws + p.off_stats);
     a.alpha = p.alpha;
     a.beta = p.beta;
@@ -384,7 +386,7 @@ static cbfs_status run_persistent(const Plan &p, const cbfs_csr *g, uint32_t *di
     a.max_rounds = p.n + 2 * (int64_t)p.R + 4;
     // barrier, error flag and statistics start at zero (plain memsets: this
     // path is never captured into a graph)
-    if ((e = hipMemsetAsync(ws + p.off_ctl, 0, 64 + sizeof(unsigned long long) * 3, st)) != hipSuccess)
+    if ((e = hipMemsetAsync(ws + p.off_ctl, 0, sizeof(unsigned int) * CTL_WORDS + 256, st)) != hipSuccess)
         return hip_fail("control reset", e);
     if ((e = hipMemsetAsync(ws + p.off_stats, 0, sizeof(long long) * 5 * (size_t)p.groups, st)) != hipSuccess)
         return hip_fail("stats reset", e);
