@@ -82,6 +82,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-clusters", type=int, default=2, help="clusters in the CPU oracle sample")
+    ap.add_argument("--no-query", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the batch of clusters shards "
@@ -207,6 +208,38 @@ def main():
                "gpu_matches_sample": same}
         print(f"[bench] cpu: {cpu}", file=sys.stderr, flush=True)
 
+    # serving: labels of the first 128 clusters (the top-128 centers) kept on
+    # the device; Poisson streams of uniform s-t queries at fixed rates
+    query = None
+    if not args.no_query:
+        from paper_2410_17226_amd import server
+        CQ = min(128, C)
+        dvm, mvm = P.labels_pack(dist[:CQ], masks[:CQ], R)
+        torch.cuda.synchronize()
+        qn = 1_000_000
+        qs, qt = synth.query_pairs(n, qn, cfg["seed"] + 5)
+        qs_d, qt_d = torch.from_numpy(qs).to(dev), torch.from_numpy(qt).to(dev)
+        ans_d = torch.empty(qn, dtype=torch.int32, device=dev)
+        P.query_batch(dvm, mvm, R, qs_d, qt_d, out=ans_d)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        P.query_batch(dvm, mvm, R, qs_d, qt_d, out=ans_d, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        kernel_ms = ev0.elapsed_time(ev1)
+        query = {"clusters": CQ, "landmarks": int(cptr[CQ]), "label_bytes": int(dvm.numel() * 4 + mvm.numel() * 8),
+                 "device_qps_1M_batch": round(qn / (kernel_ms * 1e-3), 1), "rates": []}
+        ex = server.GpuExecutor(dvm, mvm, R, max_batch=1 << 16, lanes=4)
+        for rate, count in ((1e5, 100_000), (1e6, 500_000), (1e7, 1_000_000)):
+            arr = synth.poisson_arrivals(rate, count, int(rate))
+            rep = server.serve(ex, qs[:count], qt[:count], arr)
+            same = bool(np.array_equal(rep.answers, ans_d[:count].cpu().numpy().view(np.uint32)))
+            summ = rep.summary()
+            summ.update({"offered_qps": rate, "same_as_one_batch": same})
+            query["rates"].append({k: (round(v, 2) if isinstance(v, float) else v) for k, v in summ.items()})
+            print(f"[bench] serve {rate:.0e} QPS: {summ}", file=sys.stderr, flush=True)
+        del dvm, mvm
+
     line = {
         "metric": METRIC, "value": round(gteps, 2), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak",
@@ -215,7 +248,7 @@ def main():
                    "n": n, "m_arcs": m, "clusters": C, "sources_per_cluster": int(cfg["k"]), "radius": R,
                    "group_words": stats["group_words"], "mode": stats["mode"], "slots": stats["slots"],
                    "parallelism": "single GPU"},
-        "roofline": roofline, "cpu_baseline": cpu, "plain": plain,
+        "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "query": query,
         "run_stats": stats,
     }
     print(json.dumps(line), flush=True)
