@@ -83,7 +83,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-clusters", type=int, default=2, help="clusters in the CPU oracle sample")
     ap.add_argument("--no-query", action="store_true")
+    ap.add_argument("--copy-only", type=int, default=0,
+                    help="only run one device-to-device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_only:
+        import torch
+        x = torch.empty(args.copy_only, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_only}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the batch of clusters shards "
                                    "across GPUs without communication (see DESIGN.md)", "n_gpus": args.gpus}))
@@ -128,7 +140,6 @@ def main():
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
-    P.profile_enable(True)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -139,10 +150,15 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.time() - wall0
+    step_ms = ev0.elapsed_time(ev1) / args.steps
+    # one more step with every kernel launch bracketed by HIP events on the
+    # library's stream, for the per-kernel attribution of the roofline
+    P.profile_enable(True)
+    P.run_batch(rp_d, col_d, cptr, sources, R, tuning, out=out, workspace=ws, stream=stream)
     prof = P.profile_read()
     P.profile_enable(False)
     stats = P.last_run_stats()
-    step_ms = ev0.elapsed_time(ev1) / args.steps
+    prof_steps = 1
     assert (status.cpu().numpy() == 0).all(), "a cluster reported a radius violation"
     gteps = ksum * m / (step_ms * 1e-3) / 1e9
     print(f"[bench] batched: {step_ms:.2f} ms/step ({wall / args.steps * 1e3:.2f} wall) GTEPS={gteps:.1f} "
@@ -153,14 +169,14 @@ def main():
     avg_ms = total_ms / max(1, launches)
     B_alg_step = algorithmic_bytes(n, m, stats, C, k_w, R)
     if kind == "persistent":
-        per_launch = B_alg_step * args.steps / launches
+        per_launch = B_alg_step * prof_steps / launches
         unit_note = "one batch (all groups) per launch"
     elif kind == "pull":
         W = stats["group_words"]
         per_launch = 4 * m + 4 * (n + 1) + n // 8 + 8 * W * n
         unit_note = "one dense pass over the CSR and the group state per launch"
     else:
-        per_launch = B_alg_step * args.steps / launches
+        per_launch = B_alg_step * prof_steps / launches
         unit_note = "batch bytes spread over the launches"
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     traffic = load_traffic(kind)
