@@ -37,9 +37,10 @@ constexpr int WAVES = BLOCK / 64;
 constexpr int PIECE = 256;          // max arcs per frontier work item (push)
 constexpr int TILE_ITEMS = 4096;    // merge-path items (rows + arcs) per pull block
 constexpr int IPT = TILE_ITEMS / BLOCK;
-// a pull block claims at most one vertex per row end it consumes plus one
-// partial row per thread
-constexpr int PULL_STAGE_CAP = TILE_ITEMS / 2 + BLOCK + 64;
+// a pull block claims only rows of degree >= 1 whose end item it consumes
+// (at most TILE_ITEMS / 2 + 1) plus its two boundary rows
+constexpr int PULL_STAGE_CAP = TILE_ITEMS / 2 + 64;
+constexpr int PULL_CLAIM_WORDS = TILE_ITEMS / 64 + 2;  // bitmap words spanned by a tile's rows
 constexpr int STAGE_CAP = 1024;     // LDS frontier staging capacity per push/seed block
 constexpr int MAX_W = 8;            // max words per vertex in a group
 constexpr uint32_t UNREACHED = 0xFFFFFFFFu;
@@ -228,9 +229,10 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
 }
 
 // Vertex phase for u in F_i (lines computing S_new, Delta_u, the subset write
-// and the seen update): cu = Seen_i(u).  nxt(u) receives the new bits so that
-// nxt(u) covers Seen_i(u) by the end of the round.
-template <int W, int WC>
+// and the seen update): cu = Seen_i(u).  With NXT_OR, nxt(u) receives the new
+// bits by atomic OR so that nxt(u) covers Seen_i(u) by the end of the round;
+// without it the caller stores nxt(u) itself (it owns u's row in this round).
+template <int W, int WC, bool NXT_OR = true>
 __device__ __forceinline__ void vertex_phase(const SlotArgs &s, const GroupDesc &g, const OutArgs &o,
                                              int64_t n, int32_t round, int32_t u, const uint64_t (&cu)[W])
 {
@@ -244,10 +246,12 @@ __device__ __forceinline__ void vertex_phase(const SlotArgs &s, const GroupDesc 
     }
     if (!any) return;
     store_words<W>(s.seen + (size_t)u * W, cu);
-    uint64_t *nx = nxt_buf(s, round) + (size_t)u * W;
+    if constexpr (NXT_OR) {
+        uint64_t *nx = nxt_buf(s, round) + (size_t)u * W;
 #pragma unroll
-    for (int w = 0; w < W; w++)
-        if (nw[w]) or64(nx + w, nw[w]);
+        for (int w = 0; w < W; w++)
+            if (nw[w]) or64(nx + w, nw[w]);
+    }
 #pragma unroll
     for (int j = 0; j < W / WC; j++)
         if (j < g.nc) emit_cluster<WC>(o, n, g.c0 + j, u, round, sv + j * WC, nw + j * WC, g.full + j * WC);

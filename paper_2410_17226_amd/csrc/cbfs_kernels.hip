@@ -65,7 +65,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(SlotArgs s, GraphArgs gr, GroupD
 template <int W, int WC>
 __global__ __launch_bounds__(BLOCK) void k_pull(SlotArgs s, GraphArgs gr, GroupDesc g, OutArgs o, int32_t round)
 {
-    __shared__ PullSmem sm;
+    __shared__ PullSmem<W> sm;
     clear_ahead_part(s, round, (int64_t)blockIdx.x * BLOCK + threadIdx.x, (int64_t)gridDim.x * BLOCK);
     pull_tile<W, WC>(sm, s, gr, g, o, round, blockIdx.x);
 }

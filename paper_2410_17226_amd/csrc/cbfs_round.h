@@ -17,14 +17,17 @@ struct PushSmem {
     Stager<STAGE_CAP> st;
 };
 
+template <int W>
 struct PullSmem {
+    uint64_t part[BLOCK][W];                 // partial sets of rows that cross threads, by first thread
+    uint64_t claimed[PULL_CLAIM_WORDS];      // F_{i+1} bits of the tile's rows, from word tile_row >> 6
     Stager<PULL_STAGE_CAP> st;
 };
 
 template <int W>
 union RoundSmem {
     PushSmem<W> push;
-    PullSmem pull;
+    PullSmem<W> pull;
 };
 
 // Init (Algorithm "Cluster-BFS search from S", initialization): clear one
@@ -185,11 +188,16 @@ __device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &
 // batch, then Seen_i(u) of all of them, are requested together
 // (unconditional loads with a select, so the loads overlap), and the new bits
 // are OR-ed into a register accumulator; the row stops once the accumulator
-// completes the set (EdgeMap-Dense's break).  At the row's end, or where the
-// thread's items run out, the bits not yet in Seen_i(v) are merged into
-// nxt(v) with atomics (a row may span threads and tiles).  The thread
-// consuming a row's end item also runs the vertex phase for that row if it is
-// in F_i, so that phase is coalesced across the tile's rows.
+// completes the set (EdgeMap-Dense's break).
+//
+// Every row has one owner, the thread that consumes its end item.  For a row
+// whose arcs and end all lie in this tile (a local row) the partial sets of
+// the other threads on it meet in LDS (slot of the row's first thread), and
+// the owner writes nxt(v) = Seen_i(v) | new with a plain store, claims v in an
+// LDS bitmap of the tile's rows and runs the vertex phase if v is in F_i.  The
+// claimed bitmap words that only hold local rows of this tile are stored
+// plainly, the others OR-ed.  Only the (at most two) rows that cross the
+// tile's edges merge into nxt and the frontier bitmap with global atomics.
 // ---------------------------------------------------------------------------
 template <int W>
 constexpr int pull_batch()
@@ -198,7 +206,7 @@ constexpr int pull_batch()
 }
 
 template <int W, int WC>
-__device__ void pull_tile(PullSmem &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
+__device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                           const OutArgs &o, int32_t round, int32_t t)
 {
     constexpr int NB = pull_batch<W>();
@@ -210,17 +218,27 @@ __device__ void pull_tile(PullSmem &sm, const SlotArgs &s, const GraphArgs &gr, 
 
     const int32_t r0 = gr.tile_row[t], e0 = gr.tile_edge[t];
     const int32_t r1 = gr.tile_row[t + 1], e1 = gr.tile_edge[t + 1];
+    // merge-path coordinates inside the tile: arc e of row r is item
+    // (r - r0) + (e - e0); the end item of row r is (r - r0) + (row_end[r] - e0)
+    const int32_t tile_rows = r1 - r0, tile_edges = e1 - e0;
+    const int32_t tile_items = tile_rows + tile_edges;
+    // local rows: [loc_lo, r1), those whose first arc is in this tile
+    const int32_t loc_lo = gr.row_ptr[r0] >= e0 ? r0 : r0 + 1;
+    const int32_t wbase = r0 >> 6;
+    const int32_t nclaim = (r1 >> 6) - wbase + 1;
     __syncthreads();
     stager_init(sm.st);
+#pragma unroll
+    for (int w = 0; w < W; w++) sm.part[threadIdx.x][w] = 0;
+    for (int32_t k = threadIdx.x; k < nclaim; k += BLOCK) sm.claimed[k] = 0;
     __syncthreads();
 
     // this thread's merge-path start inside the tile
-    const int32_t tile_rows = r1 - r0, tile_edges = e1 - e0;
-    const int32_t tile_items = tile_rows + tile_edges;
     int32_t rel = (int32_t)threadIdx.x * IPT;
     if (rel > tile_items) rel = tile_items;
     int32_t my_end = ((int32_t)threadIdx.x + 1) * IPT;
     if (my_end > tile_items) my_end = tile_items;
+    const int32_t my_start = rel;
     int32_t row, edge;
     {
         int32_t lo = rel > tile_edges ? rel - tile_edges : 0;
@@ -238,6 +256,32 @@ __device__ void pull_tile(PullSmem &sm, const SlotArgs &s, const GraphArgs &gr, 
 #pragma unroll
     for (int w = 0; w < W; w++) full[w] = g.full[w];
 
+    // a local row owned here whose first arcs other threads scanned: finished
+    // after the barrier, once their partial sets are in LDS
+    int32_t pend = -1;
+    uint64_t pend_cv[W], pend_acc[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) pend_cv[w] = pend_acc[w] = 0;
+
+    auto finish_local = [&](int32_t v, const uint64_t (&cv)[W], const uint64_t (&acc)[W]) {
+        bool any = false;
+#pragma unroll
+        for (int w = 0; w < W; w++) any |= acc[w] != 0;
+        const bool in_f = (bits_cur[v >> 6] >> (v & 63)) & 1ull;
+        if (in_f || any) {
+            uint64_t nv[W];
+#pragma unroll
+            for (int w = 0; w < W; w++) nv[w] = cv[w] | acc[w];
+            store_words<W>(nxt + (size_t)v * W, nv);
+        }
+        if (any) {
+            atomicOr(reinterpret_cast<unsigned long long *>(&sm.claimed[(v >> 6) - wbase]), 1ull << (v & 63));
+            stager_push(sm.st, v, row_end[v] - gr.row_ptr[v]);
+        }
+        if (in_f) vertex_phase<W, WC, false>(s, g, o, gr.n, round, v, cv);
+    };
+
+    int32_t rstart = gr.row_ptr[row];
     while (rel < my_end) {
         const int32_t rend = row_end[row];
         const int32_t budget = my_end - rel;
@@ -274,18 +318,54 @@ __device__ void pull_tile(PullSmem &sm, const SlotArgs &s, const GraphArgs &gr, 
         }
         rel += seg_end - edge;
         edge = seg_end;
-        bool any = false;
+        const bool owns_end = edge == rend && rel < my_end;
+        const int32_t first_item = (row - r0) + (rstart - e0);
+        const bool local = first_item >= 0 && row < r1;
+        if (!local) {
+            // crosses a tile edge: merge by global atomics
+            bool any = false;
 #pragma unroll
-        for (int w = 0; w < W; w++) any |= acc[w] != 0;
-        if (any) contribute<W>(sm.st, nxt, bits_next, gr.row_ptr, row, acc);
-        if (edge == rend && rel < my_end) {
-            // the row's end item is ours: vertex phase if the row is in F_i
-            if ((bits_cur[row >> 6] >> (row & 63)) & 1ull) vertex_phase<W, WC>(s, g, o, gr.n, round, row, cv);
-            rel++;
-            row++;
+            for (int w = 0; w < W; w++) any |= acc[w] != 0;
+            if (any) contribute<W>(sm.st, nxt, bits_next, gr.row_ptr, row, acc);
+            if (owns_end && ((bits_cur[row >> 6] >> (row & 63)) & 1ull))
+                vertex_phase<W, WC>(s, g, o, gr.n, round, row, cv);
+        } else if (!owns_end) {
+            // carry-out of a local row: into the slot of the row's first thread
+            uint64_t *slot = sm.part[first_item / IPT];
+#pragma unroll
+            for (int w = 0; w < W; w++)
+                if (acc[w]) atomicOr(reinterpret_cast<unsigned long long *>(slot + w), acc[w]);
+        } else if (first_item < my_start) {
+            pend = row;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                pend_cv[w] = cv[w];
+                pend_acc[w] = acc[w];
+            }
         } else {
-            break;  // items exhausted inside this row
+            finish_local(row, cv, acc);
         }
+        if (!owns_end) break;  // items exhausted inside this row
+        rel++;
+        row++;
+        rstart = rend;
+    }
+    __syncthreads();
+    if (pend >= 0) {
+        const int32_t first_item = (pend - r0) + (gr.row_ptr[pend] - e0);
+        const uint64_t *slot = sm.part[first_item / IPT];
+#pragma unroll
+        for (int w = 0; w < W; w++) pend_acc[w] |= slot[w] & ~pend_cv[w];
+        finish_local(pend, pend_cv, pend_acc);
+    }
+    __syncthreads();
+    // claimed words: plain store where every row of the word is a local row
+    for (int32_t k = threadIdx.x; k < nclaim; k += BLOCK) {
+        const uint64_t word = sm.claimed[k];
+        if (!word) continue;
+        const int64_t wi = (int64_t)wbase + k;
+        if (wi * 64 >= loc_lo && wi * 64 + 63 < r1) bits_next[wi] = word;
+        else atomicOr(reinterpret_cast<unsigned long long *>(bits_next + wi), word);
     }
     stager_flush(sm.st, gr.row_ptr, q_buf(s, round + 1), ctr_buf(s, round + 1));
 }
