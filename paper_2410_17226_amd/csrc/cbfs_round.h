@@ -192,12 +192,14 @@ __device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &
 //
 // Every row has one owner, the thread that consumes its end item.  For a row
 // whose arcs and end all lie in this tile (a local row) the partial sets of
-// the other threads on it meet in LDS (slot of the row's first thread), and
-// the owner writes nxt(v) = Seen_i(v) | new with a plain store, claims v in an
-// LDS bitmap of the tile's rows and runs the vertex phase if v is in F_i.  The
-// claimed bitmap words that only hold local rows of this tile are stored
-// plainly, the others OR-ed.  Only the (at most two) rows that cross the
-// tile's edges merge into nxt and the frontier bitmap with global atomics.
+// the threads on it meet in LDS (slot of the row's first thread), and the
+// owner writes nxt(v) = Seen_i(v) | new with a plain store and claims v in an
+// LDS bitmap of the tile's rows.  The claimed bitmap words that only hold
+// local rows of this tile are stored plainly, the others OR-ed.  Only the (at
+// most two) rows that cross the tile's edges merge into nxt and the frontier
+// bitmap with global atomics.  Finally the vertex phase runs for the rows
+// whose end item is in the tile and that are in F_i, one row per thread, so
+// its loads and stores are coalesced.
 // ---------------------------------------------------------------------------
 template <int W>
 constexpr int pull_batch()
@@ -256,12 +258,9 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
 #pragma unroll
     for (int w = 0; w < W; w++) full[w] = g.full[w];
 
-    // a local row owned here whose first arcs other threads scanned: finished
-    // after the barrier, once their partial sets are in LDS
+    // a local row owned here whose first arcs other threads scanned: its own
+    // partial set joins theirs in LDS and the row is finished after the barrier
     int32_t pend = -1;
-    uint64_t pend_cv[W], pend_acc[W];
-#pragma unroll
-    for (int w = 0; w < W; w++) pend_cv[w] = pend_acc[w] = 0;
 
     auto finish_local = [&](int32_t v, const uint64_t (&cv)[W], const uint64_t (&acc)[W]) {
         bool any = false;
@@ -278,7 +277,6 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
             atomicOr(reinterpret_cast<unsigned long long *>(&sm.claimed[(v >> 6) - wbase]), 1ull << (v & 63));
             stager_push(sm.st, v, row_end[v] - gr.row_ptr[v]);
         }
-        if (in_f) vertex_phase<W, WC, false>(s, g, o, gr.n, round, v, cv);
     };
 
     int32_t rstart = gr.row_ptr[row];
@@ -327,21 +325,13 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
 #pragma unroll
             for (int w = 0; w < W; w++) any |= acc[w] != 0;
             if (any) contribute<W>(sm.st, nxt, bits_next, gr.row_ptr, row, acc);
-            if (owns_end && ((bits_cur[row >> 6] >> (row & 63)) & 1ull))
-                vertex_phase<W, WC>(s, g, o, gr.n, round, row, cv);
-        } else if (!owns_end) {
-            // carry-out of a local row: into the slot of the row's first thread
+        } else if (!owns_end || first_item < my_start) {
+            // a local row other threads share: into the slot of its first thread
             uint64_t *slot = sm.part[first_item / IPT];
 #pragma unroll
             for (int w = 0; w < W; w++)
                 if (acc[w]) atomicOr(reinterpret_cast<unsigned long long *>(slot + w), acc[w]);
-        } else if (first_item < my_start) {
-            pend = row;
-#pragma unroll
-            for (int w = 0; w < W; w++) {
-                pend_cv[w] = cv[w];
-                pend_acc[w] = acc[w];
-            }
+            if (owns_end) pend = row;
         } else {
             finish_local(row, cv, acc);
         }
@@ -354,9 +344,19 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     if (pend >= 0) {
         const int32_t first_item = (pend - r0) + (gr.row_ptr[pend] - e0);
         const uint64_t *slot = sm.part[first_item / IPT];
+        uint64_t cv[W], acc[W];
+        load_words<W>(cur + (size_t)pend * W, cv);
 #pragma unroll
-        for (int w = 0; w < W; w++) pend_acc[w] |= slot[w] & ~pend_cv[w];
-        finish_local(pend, pend_cv, pend_acc);
+        for (int w = 0; w < W; w++) acc[w] = slot[w];
+        finish_local(pend, cv, acc);
+    }
+    // vertex phase of the rows whose end item is in this tile
+    for (int32_t v = r0 + (int32_t)threadIdx.x; v < r1; v += BLOCK) {
+        if (!((bits_cur[v >> 6] >> (v & 63)) & 1ull)) continue;
+        uint64_t cv[W];
+        load_words<W>(cur + (size_t)v * W, cv);
+        if (v < loc_lo) vertex_phase<W, WC, true>(s, g, o, gr.n, round, v, cv);  // tile-crossing row
+        else vertex_phase<W, WC, false>(s, g, o, gr.n, round, v, cv);
     }
     __syncthreads();
     // claimed words: plain store where every row of the word is a local row

@@ -1,0 +1,155 @@
+"""GPU parity at the benchmark sizes, in the benchmark's launch configuration.
+
+The whole batch runs on the device exactly as ``bench.py`` runs it (default
+tuning).  Sampled clusters are then compared word for word with the oracle, and
+more clusters are checked with the BFS certificate, which needs no oracle run.
+On the scale-22 R-MAT, queries from labels of sampled clusters are compared with
+the oracle's label query, and the distance bound of landmark labels is checked
+against plain BFS on sampled pairs.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import configs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+THREADS = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+
+
+def _log(msg):
+    print(f"[fullsize {time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _inputs(name):
+    """Both sides clean the raw graph and select clusters with their own code."""
+    import paper_2410_17226_amd as P
+    cfg = configs.WORKLOADS[name]
+    n, s, d = configs.raw_graph(name)
+    rp, col, _ = P.build_csr(n, s, d)
+    orp, ocol, _ = oracle.clean_csr(n, s, d)
+    del s, d
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+    del orp, ocol
+    if cfg["centers"] == "top_degree":
+        centers = P.top_degree(rp, cfg["count"])
+        assert np.array_equal(centers, oracle.top_degree(rp, cfg["count"]))
+    else:
+        centers = synth.random_centers(rp.size - 1, cfg["count"], cfg["seed"]).astype(np.int32)
+    cp, src = P.select_clusters(rp, col, centers, cfg["k"], cfg["hops"])
+    ocp, osrc = oracle.build_clusters(rp, col, centers, cfg["k"], cfg["hops"])
+    assert np.array_equal(cp, ocp) and np.array_equal(src, osrc)
+    _log(f"{name}: n={rp.size - 1} m={col.size} clusters={cp.size - 1} sources={cp[-1]}")
+    return cfg, rp, col, cp, src
+
+
+def _run(rp, col, cp, src, R):
+    torch = _torch()
+    import paper_2410_17226_amd as P
+    rp_d = torch.from_numpy(rp).cuda()
+    col_d = torch.from_numpy(col).cuda()
+    _log(f"run_batch C={cp.size - 1} R={R}")
+    dist, masks, st = P.run_batch(rp_d, col_d, cp, src, R)
+    torch.cuda.synchronize()
+    stats = P.last_run_stats()
+    _log(f"done: {stats}")
+    return dist, masks, st
+
+
+def _check_sampled(rp, col, cp, src, R, dist, masks, st, exact, certified):
+    status = st.cpu().numpy()
+    assert (status == 0).all(), f"clusters with status != 0: {np.nonzero(status)[0][:10]}"
+    for c in exact:
+        od, om, ost = oracle.cbfs(rp, col, [0, int(cp[c + 1] - cp[c])], src[cp[c]:cp[c + 1]], R=R,
+                                  nthreads=THREADS)
+        assert ost[0] == 0
+        gd = dist[c].cpu().numpy().view(np.uint32)
+        gm = masks[c].cpu().numpy().view(np.uint64)
+        assert np.array_equal(gd, od[0]), f"cluster {c}: dist differs"
+        assert np.array_equal(gm, om[0]), f"cluster {c}: masks differ at {np.argwhere(gm != om[0])[:5].tolist()}"
+        _log(f"cluster {c}: identical to the oracle")
+    for c in certified:
+        gd = dist[c].cpu().numpy().view(np.uint32)
+        gm = masks[c].cpu().numpy().view(np.uint64)
+        bad = oracle.certificate(rp, col, src[cp[c]:cp[c + 1]], R, gd, gm, nthreads=THREADS)
+        assert bad == 0, f"cluster {c}: {bad} certificate violations"
+    _log(f"certificate holds on clusters {list(certified)}")
+
+
+@pytest.fixture(scope="module")
+def rmat22():
+    _torch()
+    cfg, rp, col, cp, src = _inputs("rmat22")
+    dist, masks, st = _run(rp, col, cp, src, cfg["R"])
+    yield cfg, rp, col, cp, src, dist, masks, st
+    del dist, masks, st
+    _torch().cuda.empty_cache()
+
+
+def test_rmat22_batch_sampled_parity(rmat22):
+    cfg, rp, col, cp, src, dist, masks, st = rmat22
+    C = cp.size - 1
+    _check_sampled(rp, col, cp, src, cfg["R"], dist, masks, st, exact=[0, 1, C // 2, C - 1],
+                   certified=[2, 37, 100, 161, 200, 254])
+
+
+def test_rmat22_queries_sampled(rmat22):
+    """Query parity on labels of sampled clusters, and the landmark bound on
+    the 128-cluster serving labels against plain BFS."""
+    torch = _torch()
+    import paper_2410_17226_amd as P
+    cfg, rp, col, cp, src, dist, masks, st = rmat22
+    R = cfg["R"]
+    n = rp.size - 1
+    qs, qt = synth.query_pairs(n, 4096, 77)
+    qs_d, qt_d = torch.from_numpy(qs).cuda(), torch.from_numpy(qt).cuda()
+    # parity: labels of 3 clusters, the oracle's own encode of the same clusters
+    pick = [0, 5, 128]
+    ocp = np.concatenate([[0], np.cumsum([cp[c + 1] - cp[c] for c in pick])]).astype(np.int32)
+    osrc = np.concatenate([src[cp[c]:cp[c + 1]] for c in pick])
+    od, om, _ = oracle.cbfs(rp, col, ocp, osrc, R=R, nthreads=THREADS)
+    want = oracle.query_labels(od, om, qs, qt)
+    dvm, mvm = P.labels_pack(dist[pick], masks[pick], R)
+    got = P.query_batch(dvm, mvm, R, qs_d, qt_d).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, want)
+    del dvm, mvm
+    _log("query parity on 3 clusters holds")
+    # bound: the 128 serving clusters; exact distances from plain BFS (radius
+    # 0 single-source clusters of the oracle) for 64 sampled pairs
+    CQ = 128
+    dvm, mvm = P.labels_pack(dist[:CQ], masks[:CQ], R)
+    ans = P.query_batch(dvm, mvm, R, qs_d[:64], qt_d[:64]).cpu().numpy().view(np.uint32)
+    bd, _, bst = oracle.cbfs(rp, col, np.arange(65, dtype=np.int32), qs[:64], R=0, nthreads=THREADS)
+    assert (bst == 0).all()
+    exact = bd[np.arange(64), qt[:64]]
+    assert (exact != 0xFFFFFFFF).all()  # one connected component
+    assert np.all(ans.astype(np.int64) >= exact.astype(np.int64))
+    # a landmark endpoint gives the exact distance
+    lm = src[cp[0]:cp[1]]
+    lt = qt[:16]
+    ans_l = P.query_batch(dvm, mvm, R, torch.from_numpy(lm[:16].copy()).cuda(),
+                          torch.from_numpy(lt.copy()).cuda()).cpu().numpy().view(np.uint32)
+    ld, _, _ = oracle.cbfs(rp, col, np.arange(17, dtype=np.int32), lm[:16], R=0, nthreads=THREADS)
+    assert np.array_equal(ans_l, ld[np.arange(16), lt])
+    _log(f"bound holds on 64 pairs (mean slack {float(np.mean(ans.astype(np.int64) - exact)):.3f})")
+
+
+def test_grid4096_batch_sampled_parity():
+    _torch()
+    cfg, rp, col, cp, src = _inputs("grid4096")
+    dist, masks, st = _run(rp, col, cp, src, cfg["R"])
+    C = cp.size - 1
+    _check_sampled(rp, col, cp, src, cfg["R"], dist, masks, st, exact=[0, C // 2, C - 1],
+                   certified=[1, 17, 90])

@@ -146,6 +146,24 @@ def test_parity_disconnected_and_violations():
         assert_same(gpu_cbfs(rp, col, cp1, src1, 1), oracle.cbfs(orp, ocol, cp1, src1, R=1), "isolated")
 
 
+def test_parity_radius_zero():
+    """R = 0: single-source clusters (plain BFS) and a two-source cluster that
+    violates the radius, in every direction mode."""
+    ours, ref_in = prepare(*synth.rmat_edges(10, 16, seed=21), lambda rp: oracle.top_degree(rp, 6), 1, 1)
+    rp, col, _, _ = ours
+    centers = oracle.top_degree(rp, 6)
+    cp = np.arange(7, dtype=np.int32)
+    src = centers.astype(np.int32)
+    nb = int(col[rp[centers[0]]])
+    cp2 = np.concatenate([cp, [8]]).astype(np.int32)
+    src2 = np.concatenate([src, [centers[1], nb if nb != centers[1] else int(col[rp[centers[1]]])]]).astype(np.int32)
+    for tun in (None, dict(force_pull=1), dict(alpha=-1.0), dict(mode=2, concurrent_groups=3, group_words=1)):
+        gpu = gpu_cbfs(rp, col, cp2, src2, 0, tuning_of(tun))
+        ref = oracle.cbfs(rp, col, cp2, src2, R=0)
+        assert ref[2][-1] == oracle.E_RADIUS and (ref[2][:-1] == 0).all()
+        assert_same(gpu, ref, f"R=0 {tun}")
+
+
 def workload_inputs(name):
     cfg = configs.WORKLOADS[name]
     n, s, d = configs.raw_graph(name)

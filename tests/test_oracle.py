@@ -264,6 +264,25 @@ def read_fixture(golden_dir):
     return fx
 
 
+def test_radius_zero():
+    """R = 0: a single-source cluster is plain BFS (scipy); a second source
+    always sits at a non-zero offset somewhere (at itself), a violation."""
+    n, s, d = synth.random_graph(80, 0.06, 4)
+    rp, col, _ = oracle.clean_csr(n, s, d)
+    nv = rp.size - 1
+    A = sp.csr_matrix((np.ones(col.size), col, rp), shape=(nv, nv))
+    D = shortest_path(A, unweighted=True)
+    src = np.array([0, 7, nv - 1], np.int32)
+    dist, masks, st = oracle.cbfs(rp, col, np.arange(4, dtype=np.int32), src, R=0)
+    assert masks.shape == (3, 1, nv, 1) and (st == 0).all()
+    for i, x in enumerate(src):
+        assert np.array_equal(dist[i].astype(np.int64), D[x].astype(np.int64))
+        assert np.all(masks[i, 0, :, 0] == 1)
+    nb = int(col[rp[0]])
+    _, _, st2 = oracle.cbfs(rp, col, [0, 2], [0, nb], R=0)
+    assert st2[0] == oracle.E_RADIUS
+
+
 def test_hand_worked_fixture(golden_dir):
     fx = read_fixture(golden_dir)
     rp, col = csr_of(fx["n"], fx["edges"])
