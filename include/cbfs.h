@@ -177,7 +177,10 @@ typedef struct {
     int32_t schedule;          /* persistent mode: 0 = fixed stride over the items
                                   (default), 1 = blocks take work items from a shared
                                   counter                                               */
-    int32_t reserved;
+    float gamma;               /* a pull round ORs every neighbour's set, without the
+                                  frontier-bitmap test, when sum deg(F) > gamma * m
+                                  (the test would pass for most arcs anyway); 0 = auto
+                                  (0.5), < 0 = always test                              */
 } cbfs_tuning;
 
 /* Bytes of device workspace cbfs_run_batch needs for these arguments. */

@@ -49,7 +49,7 @@ class _Tuning(ctypes.Structure):
                 ("concurrent_groups", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("alpha", ctypes.c_float), ("beta", ctypes.c_float),
                 ("force_pull", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("gamma", ctypes.c_float)]
 
 
 class _RunStats(ctypes.Structure):
@@ -75,10 +75,11 @@ class Tuning:
     force_pull: int = 0
     blocks_per_cu: int = 0
     schedule: int = 0
+    gamma: float = 0.0
 
     def _c(self) -> _Tuning:
         return _Tuning(self.mode, self.group_words, self.concurrent_groups, self.block_size,
-                       self.alpha, self.beta, self.force_pull, self.blocks_per_cu, self.schedule, 0)
+                       self.alpha, self.beta, self.force_pull, self.blocks_per_cu, self.schedule, self.gamma)
 
 
 def load():

@@ -35,12 +35,11 @@ namespace cbfs {
 constexpr int BLOCK = 256;          // threads per block (4 waves of 64)
 constexpr int WAVES = BLOCK / 64;
 constexpr int PIECE = 256;          // max arcs per frontier work item (push)
-constexpr int TILE_ITEMS = 4096;    // merge-path items (rows + arcs) per pull block
+constexpr int TILE_ITEMS = 8192;    // merge-path items (rows + arcs) per pull block
 constexpr int IPT = TILE_ITEMS / BLOCK;
-// a pull block claims only rows of degree >= 1 whose end item it consumes
-// (at most TILE_ITEMS / 2 + 1) plus its two boundary rows
-constexpr int PULL_STAGE_CAP = TILE_ITEMS / 2 + 64;
+static_assert(TILE_ITEMS + 2 <= 65535, "pull tiles stage row ends as 16-bit offsets");
 constexpr int PULL_CLAIM_WORDS = TILE_ITEMS / 64 + 2;  // bitmap words spanned by a tile's rows
+static_assert(PULL_CLAIM_WORDS <= BLOCK, "one claimed word per thread at a pull tile's flush");
 constexpr int STAGE_CAP = 1024;     // LDS frontier staging capacity per push/seed block
 constexpr int MAX_W = 8;            // max words per vertex in a group
 constexpr uint32_t UNREACHED = 0xFFFFFFFFu;
@@ -229,32 +228,38 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
 }
 
 // Vertex phase for u in F_i (lines computing S_new, Delta_u, the subset write
-// and the seen update): cu = Seen_i(u).  With NXT_OR, nxt(u) receives the new
-// bits by atomic OR so that nxt(u) covers Seen_i(u) by the end of the round;
+// and the seen update), one cluster of the group at a time: new = Seen_i(u) \
+// Seen_{i-1}(u) from cur and seen.  With NXT_OR, nxt(u) receives the new bits
+// by atomic OR so that nxt(u) covers Seen_i(u) by the end of the round;
 // without it the caller stores nxt(u) itself (it owns u's row in this round).
 template <int W, int WC, bool NXT_OR = true>
 __device__ __forceinline__ void vertex_phase(const SlotArgs &s, const GroupDesc &g, const OutArgs &o,
-                                             int64_t n, int32_t round, int32_t u, const uint64_t (&cu)[W])
+                                             int64_t n, int32_t round, int32_t u)
 {
-    uint64_t sv[W], nw[W];
-    load_words<W>(s.seen + (size_t)u * W, sv);
-    bool any = false;
+    const uint64_t *cp = cur_buf(s, round) + (size_t)u * W;
+    uint64_t *sp = s.seen + (size_t)u * W;
+    uint64_t *np = nxt_buf(s, round) + (size_t)u * W;
+#pragma unroll 1
+    for (int j = 0; j < W / WC; j++) {
+        if (j >= g.nc) break;
+        uint64_t cu[WC], sv[WC], nw[WC];
+        uint64_t any = 0;
 #pragma unroll
-    for (int w = 0; w < W; w++) {
-        nw[w] = cu[w] & ~sv[w];
-        any |= nw[w] != 0;
+        for (int x = 0; x < WC; x++) {
+            cu[x] = cp[j * WC + x];
+            sv[x] = sp[j * WC + x];
+            nw[x] = cu[x] & ~sv[x];
+            any |= nw[x];
+        }
+        if (!any) continue;
+#pragma unroll
+        for (int x = 0; x < WC; x++) {
+            sp[j * WC + x] = cu[x];
+            if constexpr (NXT_OR)
+                if (nw[x]) or64(np + j * WC + x, nw[x]);
+        }
+        emit_cluster<WC>(o, n, g.c0 + j, u, round, sv, nw, g.full + j * WC);
     }
-    if (!any) return;
-    store_words<W>(s.seen + (size_t)u * W, cu);
-    if constexpr (NXT_OR) {
-        uint64_t *nx = nxt_buf(s, round) + (size_t)u * W;
-#pragma unroll
-        for (int w = 0; w < W; w++)
-            if (nw[w]) or64(nx + w, nw[w]);
-    }
-#pragma unroll
-    for (int j = 0; j < W / WC; j++)
-        if (j < g.nc) emit_cluster<WC>(o, n, g.c0 + j, u, round, sv + j * WC, nw + j * WC, g.full + j * WC);
 }
 
 // Exclusive block scan of one int per thread; *total receives the sum.

@@ -32,7 +32,7 @@ struct PersistArgs {
     unsigned long long *work;   // [3] per-round work counters
     int32_t *err;               // 0 ok, 1 barrier timeout, 2 round limit
     long long *stats;           // [num_groups][5]: rounds, push, pull, sum |F|, sum deg(F)
-    float alpha, beta;
+    float alpha, beta, gamma;
     int32_t force_pull;
     int32_t schedule;           // 0 fixed stride, 1 shared work counter
     int64_t max_rounds;
@@ -46,7 +46,7 @@ hipError_t launch_seed(int W, int WC, const SlotArgs &s, const GraphArgs &gr, co
 hipError_t launch_push(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                        const OutArgs &o, int32_t round, int64_t nq, hipStream_t st);
 hipError_t launch_pull(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                       const OutArgs &o, int32_t round, hipStream_t st);
+                       const OutArgs &o, int32_t round, int32_t test_frontier, hipStream_t st);
 hipError_t launch_finalize(int W, int WC, const SlotArgs &s, int64_t n, const GroupDesc &g, const OutArgs &o,
                            hipStream_t st);
 // Blocks of the persistent kernel on the current device: per_cu per compute

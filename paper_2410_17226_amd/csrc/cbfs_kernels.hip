@@ -63,11 +63,12 @@ __global__ __launch_bounds__(BLOCK) void k_push(SlotArgs s, GraphArgs gr, GroupD
 }
 
 template <int W, int WC>
-__global__ __launch_bounds__(BLOCK) void k_pull(SlotArgs s, GraphArgs gr, GroupDesc g, OutArgs o, int32_t round)
+__global__ __launch_bounds__(BLOCK) void k_pull(SlotArgs s, GraphArgs gr, GroupDesc g, OutArgs o, int32_t round,
+                                               int32_t test_frontier)
 {
     __shared__ PullSmem<W> sm;
     clear_ahead_part(s, round, (int64_t)blockIdx.x * BLOCK + threadIdx.x, (int64_t)gridDim.x * BLOCK);
-    pull_tile<W, WC>(sm, s, gr, g, o, round, blockIdx.x);
+    pull_tile<W, WC>(sm, s, gr, g, o, round, blockIdx.x, test_frontier != 0);
 }
 
 template <int W, int WC>
@@ -285,6 +286,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                     else if (a.alpha < 0.f) dense = 0;
                     else if (!dense) dense = (double)(verts + degsum) > (double)a.gr.m / a.alpha;
                     else dense = (double)verts > (double)a.gr.n / a.beta;
+                    // 2: pull over every neighbour, without the membership test
+                    if (dense && a.gamma > 0.f && (double)degsum > (double)a.gamma * (double)a.gr.m) dense = 2;
+                    else if (dense) dense = 1;
                     s_dense[sl_me] = dense;
                     work = dense ? a.gr.ntiles : (pieces + BLOCK - 1) / BLOCK;
                     // bitmap words of F_{i-1} to clear: sparse through its queue
@@ -361,7 +365,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                         __syncthreads();
                         clear_item(s_slot, round, s_sparse[sl] != 0, s_nprev[sl], local - s_work[sl]);
                     } else if (s_dense[sl]) {
-                        pull_tile<W, WC>(sm.pull, s_slot, a.gr, s_group, a.o, round, (int32_t)local);
+                        pull_tile<W, WC>(sm.pull, s_slot, a.gr, s_group, a.o, round, (int32_t)local,
+                                         s_dense[sl] == 1);
                     } else {
                         push_chunk<W, WC>(sm.push, s_slot, a.gr, s_group, a.o, round, s_nq[sl], local);
                     }
@@ -430,9 +435,9 @@ hipError_t launch_push(int W, int WC, const SlotArgs &s, const GraphArgs &gr, co
 }
 
 hipError_t launch_pull(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                       const OutArgs &o, int32_t round, hipStream_t st)
+                       const OutArgs &o, int32_t round, int32_t test_frontier, hipStream_t st)
 {
-    CBFS_DISPATCH(W, WC, (k_pull<W, WC><<<(unsigned)gr.ntiles, BLOCK, 0, st>>>(s, gr, g, o, round)));
+    CBFS_DISPATCH(W, WC, (k_pull<W, WC><<<(unsigned)gr.ntiles, BLOCK, 0, st>>>(s, gr, g, o, round, test_frontier)));
     return hipGetLastError();
 }
 

@@ -19,9 +19,12 @@ struct PushSmem {
 
 template <int W>
 struct PullSmem {
-    uint64_t part[BLOCK][W];                 // partial sets of rows that cross threads, by first thread
+    uint64_t part[BLOCK][W];                 // partial sets of rows shared by threads, by first thread
     uint64_t claimed[PULL_CLAIM_WORDS];      // F_{i+1} bits of the tile's rows, from word tile_row >> 6
-    Stager<PULL_STAGE_CAP> st;
+    uint16_t rend[TILE_ITEMS + 2];           // row_end of the tile's rows minus tile_edge (clamped)
+    int tmp[WAVES + 1];
+    unsigned long long degsum;
+    long long base;
 };
 
 template <int W>
@@ -141,7 +144,7 @@ __device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &
         cnt = hi > lo ? hi - lo : 0;
         uint64_t cu[W];
         load_words<W>(cur + (size_t)u * W, cu);
-        if (p == 0) vertex_phase<W, WC>(s, g, o, gr.n, round, u, cu);
+        if (p == 0) vertex_phase<W, WC>(s, g, o, gr.n, round, u);
         sm.estart[threadIdx.x] = lo;
 #pragma unroll
         for (int w = 0; w < W; w++) sm.cu[threadIdx.x * W + w] = cu[w];
@@ -181,59 +184,96 @@ __device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &
 
 // ---------------------------------------------------------------------------
 // Round i, pull direction (EdgeMap-Dense), one merge-path tile of TILE_ITEMS
-// items (arcs and row ends) of the CSR.  Each thread walks IPT consecutive
-// items row segment by row segment.  For a row v it loads Seen_i(v) once (a
-// finished row, holding every source, is skipped: EdgeMap's Cond_F), then
-// processes its arcs in batches: the frontier bits of all neighbours in the
-// batch, then Seen_i(u) of all of them, are requested together
-// (unconditional loads with a select, so the loads overlap), and the new bits
-// are OR-ed into a register accumulator; the row stops once the accumulator
-// completes the set (EdgeMap-Dense's break).
+// items (arcs and row ends) of the CSR.  The tile's row ends are first staged
+// in LDS (as offsets from the tile's first arc), so that each thread finds its
+// merge-path start and walks its rows without global row-pointer loads.  Each
+// thread then walks IPT consecutive items row segment by row segment.  For a
+// row v it loads Seen_i(v) once (a finished row, holding every source, is
+// skipped: EdgeMap's Cond_F), then processes its arcs in batches: the frontier
+// bits of all neighbours in the batch, then Seen_i(u) of all of them, are
+// requested together (unconditional loads with a select, so the loads
+// overlap), and the new bits are OR-ed into a register accumulator; the row
+// stops once the accumulator completes the set (EdgeMap-Dense's break).
+// Without test_frontier every neighbour's set is OR-ed: a neighbour outside
+// F_i has Seen_i(u) = Seen_{i-1}(u), already inside Seen_i(v), so this only
+// saves the bitmap lookups when F_i holds most of the arcs.
 //
 // Every row has one owner, the thread that consumes its end item.  For a row
 // whose arcs and end all lie in this tile (a local row) the partial sets of
 // the threads on it meet in LDS (slot of the row's first thread), and the
 // owner writes nxt(v) = Seen_i(v) | new with a plain store and claims v in an
-// LDS bitmap of the tile's rows.  The claimed bitmap words that only hold
-// local rows of this tile are stored plainly, the others OR-ed.  Only the (at
-// most two) rows that cross the tile's edges merge into nxt and the frontier
-// bitmap with global atomics.  Finally the vertex phase runs for the rows
-// whose end item is in the tile and that are in F_i, one row per thread, so
-// its loads and stores are coalesced.
+// LDS bitmap of the tile's rows.  Only the (at most two) rows that cross the
+// tile's edges merge into nxt and the frontier bitmap with global atomics; a
+// claim they win joins the LDS bitmap.  Then the vertex phase runs for the
+// rows whose end item is in the tile and that are in F_i, one row per thread,
+// so its loads and stores are coalesced.  Finally the claimed words go to the
+// frontier bitmap (plain stores where a word only holds local rows of this
+// tile) and the claimed rows, expanded into their pieces, to the F_{i+1}
+// queue at offsets from one block scan.
 // ---------------------------------------------------------------------------
 template <int W>
 constexpr int pull_batch()
 {
-    return W <= 2 ? 8 : (W <= 4 ? 4 : 2);
+    return W <= 2 ? 8 : (W <= 4 ? 4 : 1);
+}
+
+// OR x into nxt(v) for a row whose arcs span several tiles; true if this call
+// added a bit and won v's claim in the frontier bitmap.
+template <int W>
+__device__ __forceinline__ bool merge_global(uint64_t *nxt, uint64_t *bits_next, int32_t v, const uint64_t (&x)[W])
+{
+    uint64_t *p = nxt + (size_t)v * W;
+    uint64_t added = 0;
+#pragma unroll
+    for (int w = 0; w < W; w++)
+        if (x[w]) {
+            const uint64_t old = or64(p + w, x[w]);
+            added |= x[w] & ~old;
+        }
+    if (!added) return false;
+    const unsigned long long bit = 1ull << (v & 63);
+    const unsigned long long old = atomicOr(reinterpret_cast<unsigned long long *>(bits_next + (v >> 6)), bit);
+    return !(old & bit);
 }
 
 template <int W, int WC>
 __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                          const OutArgs &o, int32_t round, int32_t t)
+                          const OutArgs &o, int32_t round, int32_t t, bool test_frontier)
 {
     constexpr int NB = pull_batch<W>();
     const uint64_t *cur = cur_buf(s, round);
     uint64_t *nxt = nxt_buf(s, round);
     const uint64_t *bits_cur = bits_buf(s, round % 3);
     uint64_t *bits_next = bits_buf(s, (round + 1) % 3);
-    const int32_t *row_end = gr.row_ptr + 1;
 
     const int32_t r0 = gr.tile_row[t], e0 = gr.tile_edge[t];
     const int32_t r1 = gr.tile_row[t + 1], e1 = gr.tile_edge[t + 1];
     // merge-path coordinates inside the tile: arc e of row r is item
-    // (r - r0) + (e - e0); the end item of row r is (r - r0) + (row_end[r] - e0)
+    // (r - r0) + (e - e0); the end item of row r is (r - r0) + (row_end[r] - e0).
+    // Rows r0 .. r1 - 1 end in this tile; row r1 (if it exists) may have arcs
+    // here and end in a later tile.
     const int32_t tile_rows = r1 - r0, tile_edges = e1 - e0;
     const int32_t tile_items = tile_rows + tile_edges;
+    const int32_t start_r0 = gr.row_ptr[r0];  // may lie before e0
+    const int32_t end_r1 = (int64_t)r1 < gr.n ? gr.row_ptr[r1 + 1] : e1;
     // local rows: [loc_lo, r1), those whose first arc is in this tile
-    const int32_t loc_lo = gr.row_ptr[r0] >= e0 ? r0 : r0 + 1;
+    const int32_t loc_lo = start_r0 >= e0 ? r0 : r0 + 1;
     const int32_t wbase = r0 >> 6;
     const int32_t nclaim = (r1 >> 6) - wbase + 1;
     __syncthreads();
-    stager_init(sm.st);
 #pragma unroll
     for (int w = 0; w < W; w++) sm.part[threadIdx.x][w] = 0;
     for (int32_t k = threadIdx.x; k < nclaim; k += BLOCK) sm.claimed[k] = 0;
+    for (int32_t k = threadIdx.x; k <= tile_rows; k += BLOCK) {
+        const int32_t r = r0 + k;
+        int32_t x = ((int64_t)r < gr.n ? gr.row_ptr[r + 1] : e1) - e0;
+        sm.rend[k] = (uint16_t)(x > tile_edges + 1 ? tile_edges + 1 : x);
+    }
+    if (threadIdx.x == 0) sm.degsum = 0;
     __syncthreads();
+    // row_end[r] for a row of the tile (exact for r < r1; past e1 for r1)
+    auto rend_of = [&](int32_t r) { return e0 + (int32_t)sm.rend[r - r0]; };
+    auto rstart_of = [&](int32_t r) { return r == r0 ? start_r0 : e0 + (int32_t)sm.rend[r - 1 - r0]; };
 
     // this thread's merge-path start inside the tile
     int32_t rel = (int32_t)threadIdx.x * IPT;
@@ -247,7 +287,7 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         int32_t hi = rel < tile_rows ? rel : tile_rows;
         while (lo < hi) {
             int32_t mid = (lo + hi) >> 1;
-            if (row_end[r0 + mid] - e0 <= rel - mid - 1) lo = mid + 1;
+            if ((int32_t)sm.rend[mid] <= rel - mid - 1) lo = mid + 1;
             else hi = mid;
         }
         row = r0 + lo;
@@ -258,10 +298,9 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
 #pragma unroll
     for (int w = 0; w < W; w++) full[w] = g.full[w];
 
-    // a local row owned here whose first arcs other threads scanned: its own
-    // partial set joins theirs in LDS and the row is finished after the barrier
-    int32_t pend = -1;
-
+    auto claim_lds = [&](int32_t v) {
+        atomicOr(reinterpret_cast<unsigned long long *>(&sm.claimed[(v >> 6) - wbase]), 1ull << (v & 63));
+    };
     auto finish_local = [&](int32_t v, const uint64_t (&cv)[W], const uint64_t (&acc)[W]) {
         bool any = false;
 #pragma unroll
@@ -273,15 +312,15 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
             for (int w = 0; w < W; w++) nv[w] = cv[w] | acc[w];
             store_words<W>(nxt + (size_t)v * W, nv);
         }
-        if (any) {
-            atomicOr(reinterpret_cast<unsigned long long *>(&sm.claimed[(v >> 6) - wbase]), 1ull << (v & 63));
-            stager_push(sm.st, v, row_end[v] - gr.row_ptr[v]);
-        }
+        if (any) claim_lds(v);
     };
 
-    int32_t rstart = gr.row_ptr[row];
+    // a local row owned here whose first arcs other threads scanned: its own
+    // partial set joins theirs in LDS and the row is finished after the barrier
+    int32_t pend = -1;
+    int32_t rstart = rel < my_end ? rstart_of(row) : 0;
     while (rel < my_end) {
-        const int32_t rend = row_end[row];
+        const int32_t rend = rend_of(row);
         const int32_t budget = my_end - rel;
         const int32_t seg_end = rend < edge + budget ? rend : edge + budget;
         uint64_t cv[W], acc[W];
@@ -297,11 +336,16 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
             bool hit[NB];
 #pragma unroll
             for (int j = 0; j < NB; j++) u[j] = (e + j < seg_end) ? gr.col[e + j] : row;
-            uint64_t bw[NB];
+            if (test_frontier) {
+                uint64_t bw[NB];
 #pragma unroll
-            for (int j = 0; j < NB; j++) bw[j] = bits_cur[u[j] >> 6];
+                for (int j = 0; j < NB; j++) bw[j] = bits_cur[u[j] >> 6];
 #pragma unroll
-            for (int j = 0; j < NB; j++) hit[j] = ((bw[j] >> (u[j] & 63)) & 1ull) && (e + j < seg_end);
+                for (int j = 0; j < NB; j++) hit[j] = ((bw[j] >> (u[j] & 63)) & 1ull) && (e + j < seg_end);
+            } else {
+#pragma unroll
+                for (int j = 0; j < NB; j++) hit[j] = e + j < seg_end;
+            }
             uint64_t cu[NB][W];
 #pragma unroll
             for (int j = 0; j < NB; j++) load_words<W>(cur + (size_t)(hit[j] ? u[j] : row) * W, cu[j]);
@@ -324,7 +368,7 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
             bool any = false;
 #pragma unroll
             for (int w = 0; w < W; w++) any |= acc[w] != 0;
-            if (any) contribute<W>(sm.st, nxt, bits_next, gr.row_ptr, row, acc);
+            if (any && merge_global<W>(nxt, bits_next, row, acc)) claim_lds(row);
         } else if (!owns_end || first_item < my_start) {
             // a local row other threads share: into the slot of its first thread
             uint64_t *slot = sm.part[first_item / IPT];
@@ -342,7 +386,7 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     }
     __syncthreads();
     if (pend >= 0) {
-        const int32_t first_item = (pend - r0) + (gr.row_ptr[pend] - e0);
+        const int32_t first_item = (pend - r0) + (rstart_of(pend) - e0);
         const uint64_t *slot = sm.part[first_item / IPT];
         uint64_t cv[W], acc[W];
         load_words<W>(cur + (size_t)pend * W, cv);
@@ -353,21 +397,50 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     // vertex phase of the rows whose end item is in this tile
     for (int32_t v = r0 + (int32_t)threadIdx.x; v < r1; v += BLOCK) {
         if (!((bits_cur[v >> 6] >> (v & 63)) & 1ull)) continue;
-        uint64_t cv[W];
-        load_words<W>(cur + (size_t)v * W, cv);
-        if (v < loc_lo) vertex_phase<W, WC, true>(s, g, o, gr.n, round, v, cv);  // tile-crossing row
-        else vertex_phase<W, WC, false>(s, g, o, gr.n, round, v, cv);
+        if (v < loc_lo) vertex_phase<W, WC, true>(s, g, o, gr.n, round, v);  // tile-crossing row
+        else vertex_phase<W, WC, false>(s, g, o, gr.n, round, v);
     }
     __syncthreads();
-    // claimed words: plain store where every row of the word is a local row
-    for (int32_t k = threadIdx.x; k < nclaim; k += BLOCK) {
-        const uint64_t word = sm.claimed[k];
-        if (!word) continue;
-        const int64_t wi = (int64_t)wbase + k;
-        if (wi * 64 >= loc_lo && wi * 64 + 63 < r1) bits_next[wi] = word;
-        else atomicOr(reinterpret_cast<unsigned long long *>(bits_next + wi), word);
+
+    // frontier flush: one claimed word per thread (nclaim <= BLOCK)
+    auto deg_of = [&](int32_t v) { return (v == r1 ? end_r1 : rend_of(v)) - rstart_of(v); };
+    uint64_t word = 0;
+    int pieces = 0;
+    if ((int32_t)threadIdx.x < nclaim) {
+        word = sm.claimed[threadIdx.x];
+        if (word) {
+            const int64_t wi = (int64_t)wbase + threadIdx.x;
+            if (wi * 64 >= loc_lo && wi * 64 + 63 < r1) bits_next[wi] = word;
+            else atomicOr(reinterpret_cast<unsigned long long *>(bits_next + wi), word);
+            unsigned long long dsum = 0;
+            for (uint64_t x = word; x; x &= x - 1) {
+                const int32_t v = (int32_t)(wi * 64 + __builtin_ctzll(x));
+                const int32_t d = deg_of(v);
+                pieces += pieces_of(d);
+                dsum += (unsigned long long)d;
+            }
+            atomicAdd(&sm.degsum, dsum);
+        }
     }
-    stager_flush(sm.st, gr.row_ptr, q_buf(s, round + 1), ctr_buf(s, round + 1));
+    int total;
+    const int off = block_exclusive_scan(pieces, sm.tmp, &total);
+    int cnt_total;
+    block_exclusive_scan(__popcll(word), sm.tmp, &cnt_total);
+    if (total == 0) return;  // block-uniform
+    unsigned long long *ctr_next = ctr_buf(s, round + 1);
+    if (threadIdx.x == 0) {
+        sm.base = (long long)atomicAdd(ctr_next + 0, (unsigned long long)total);
+        atomicAdd(ctr_next + 1, (unsigned long long)cnt_total);
+        atomicAdd(ctr_next + 2, sm.degsum);
+    }
+    __syncthreads();
+    int64_t *dst = q_buf(s, round + 1) + sm.base + off;
+    const int64_t wi = (int64_t)wbase + threadIdx.x;
+    for (uint64_t x = word; x; x &= x - 1) {
+        const int32_t v = (int32_t)(wi * 64 + __builtin_ctzll(x));
+        const int pc = pieces_of(deg_of(v));
+        for (int p = 0; p < pc; p++) *dst++ = ((int64_t)p << 32) | (int64_t)(uint32_t)v;
+    }
 }
 
 // ---------------------------------------------------------------------------

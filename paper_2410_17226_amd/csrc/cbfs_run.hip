@@ -101,7 +101,7 @@ struct Plan {
     int32_t groups = 0;
     int32_t slots = 1;
     int32_t mode = CBFS_MODE_PERSISTENT;
-    float alpha = 15.0f, beta = 20.0f;
+    float alpha = 15.0f, beta = 20.0f, gamma = 0.5f;
     int32_t force_pull = 0;
     int32_t blocks_per_cu = 0, schedule = 0;
     int32_t ntiles = 0;
@@ -172,6 +172,7 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
         if (t->alpha != 0.0f) p.alpha = t->alpha;
         if (t->beta < 0.0f) return fail(CBFS_E_ARG, "cbfs_tuning: beta < 0");
         if (t->beta != 0.0f) p.beta = t->beta;
+        if (t->gamma != 0.0f) p.gamma = t->gamma;
         p.force_pull = t->force_pull;
         if (t->concurrent_groups < 0 || t->concurrent_groups > MAX_SLOTS)
             return fail(CBFS_E_ARG, "cbfs_tuning: concurrent_groups outside [0, 64]");
@@ -347,7 +348,11 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
             (dense ? rs.pull_rounds : rs.push_rounds)++;
             rs.frontier_vertices += verts;
             rs.frontier_arcs += degsum;
-            if (dense) e = PROF(CBFS_KERNEL_PULL, st, launch_pull(p.W, p.WC, s, gr, gd, o, round, st));
+            // a frontier carrying most of the arcs: every neighbour's set is
+            // OR-ed without the membership test (the sets of non-members add
+            // nothing new, Section 3.2, and the test would pass for most arcs)
+            const int32_t test = !(p.gamma > 0.0f && (double)degsum > (double)p.gamma * (double)p.m);
+            if (dense) e = PROF(CBFS_KERNEL_PULL, st, launch_pull(p.W, p.WC, s, gr, gd, o, round, test, st));
             else e = PROF(CBFS_KERNEL_PUSH, st, launch_push(p.W, p.WC, s, gr, gd, o, round, pieces, st));
             if (e != hipSuccess) return hip_fail(dense ? "pull" : "push", e);
         }
@@ -381,6 +386,7 @@ static cbfs_status run_persistent(const Plan &p, const cbfs_csr *g, uint32_t *di
     a.stats = (long long *)(ws + p.off_stats);
     a.alpha = p.alpha;
     a.beta = p.beta;
+    a.gamma = p.gamma;
     a.force_pull = p.force_pull;
     a.schedule = p.schedule;
     a.max_rounds = p.n + 2 * (int64_t)p.R + 4;
