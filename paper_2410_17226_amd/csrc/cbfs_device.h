@@ -360,30 +360,31 @@ __device__ __forceinline__ void stager_flush(Stager<CAP> &st, const int32_t *row
 }
 
 // Claim v for F_{i+1} (the compare-and-swap on r[v] of Algorithm "Cluster-BFS
-// search from S", here an atomic OR on a membership bitmap: first setter wins).
+// search from S", here an atomic OR on a membership bitmap: first setter
+// wins).  Bits only go from 0 to 1 within a round, so a plain load that
+// already shows v's bit saves the atomic.
 template <int CAP>
 __device__ __forceinline__ void claim(Stager<CAP> &st, uint64_t *bits_next, int32_t v, int32_t deg)
 {
     const unsigned long long bit = 1ull << (v & 63);
-    const unsigned long long old = atomicOr(reinterpret_cast<unsigned long long *>(bits_next + (v >> 6)), bit);
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(bits_next + (v >> 6));
+    if (*w & bit) return;
+    const unsigned long long old = atomicOr(w, bit);
     if (!(old & bit)) stager_push(st, v, deg);
 }
 
-// Contribute x (bits of a neighbour's set) to v: OR the bits not yet in
-// Seen_i(v) into nxt(v); claim v if this call added any of them.
+// Contribute x = Seen_i(u) \ Seen_i(v), non-empty, to v: OR it into nxt(v)
+// (atomics whose old value is not needed) and claim v.  v joins F_{i+1}
+// whoever's OR lands first: x holds bits v did not have in round i.
 template <int W, int CAP>
 __device__ __forceinline__ void contribute(Stager<CAP> &st, uint64_t *nxt, uint64_t *bits_next,
                                           const int32_t *row_ptr, int32_t v, const uint64_t (&x)[W])
 {
     uint64_t *p = nxt + (size_t)v * W;
-    uint64_t added = 0;
 #pragma unroll
     for (int w = 0; w < W; w++)
-        if (x[w]) {
-            const uint64_t old = or64(p + w, x[w]);
-            added |= x[w] & ~old;
-        }
-    if (added) claim(st, bits_next, v, row_ptr[v + 1] - row_ptr[v]);
+        if (x[w]) or64(p + w, x[w]);
+    claim(st, bits_next, v, row_ptr[v + 1] - row_ptr[v]);
 }
 
 }  // namespace cbfs

@@ -217,20 +217,15 @@ constexpr int pull_batch()
     return W <= 2 ? 8 : (W <= 4 ? 4 : 1);
 }
 
-// OR x into nxt(v) for a row whose arcs span several tiles; true if this call
-// added a bit and won v's claim in the frontier bitmap.
+// OR x (non-empty, bits v lacked in round i) into nxt(v) for a row whose arcs
+// span several tiles; true if this call won v's claim in the frontier bitmap.
 template <int W>
 __device__ __forceinline__ bool merge_global(uint64_t *nxt, uint64_t *bits_next, int32_t v, const uint64_t (&x)[W])
 {
     uint64_t *p = nxt + (size_t)v * W;
-    uint64_t added = 0;
 #pragma unroll
     for (int w = 0; w < W; w++)
-        if (x[w]) {
-            const uint64_t old = or64(p + w, x[w]);
-            added |= x[w] & ~old;
-        }
-    if (!added) return false;
+        if (x[w]) or64(p + w, x[w]);
     const unsigned long long bit = 1ull << (v & 63);
     const unsigned long long old = atomicOr(reinterpret_cast<unsigned long long *>(bits_next + (v >> 6)), bit);
     return !(old & bit);
