@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-clusters", type=int, default=2, help="clusters in the CPU oracle sample")
     ap.add_argument("--no-query", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the launch knobs on the first 16 clusters before timing (untimed)")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run one device-to-device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -128,6 +130,15 @@ def main():
     rp_d = torch.from_numpy(rp).to(dev)
     col_d = torch.from_numpy(col).to(dev)
     tuning = P.Tuning(mode=args.mode, group_words=args.group_words, concurrent_groups=args.slots)
+    tuned = None
+    if args.tune:
+        t0 = time.time()
+        tuning, trials = P.autotune(rp_d, col_d, cptr, sources, R, start=tuning, sample_clusters=16)
+        tuned = {"chosen": vars(tuning), "trials": len(trials), "seconds": round(time.time() - t0, 2),
+                 "best_trial_ms": round(min(ms for _, ms, _ in trials if ms >= 0), 2)}
+        print(f"[bench] autotune: {tuned}", file=sys.stderr, flush=True)
+        for t, ms, mode in trials:
+            print(f"[bench]   trial mode={mode} {vars(t)} {ms:.2f} ms", file=sys.stderr, flush=True)
     dist = torch.empty((C, n), dtype=torch.int32, device=dev)
     masks = torch.empty((C, 2 * R + 1, n, k_w), dtype=torch.int64, device=dev)
     status = torch.empty(C, dtype=torch.int32, device=dev)
@@ -264,7 +275,7 @@ def main():
                    "n": n, "m_arcs": m, "clusters": C, "sources_per_cluster": int(cfg["k"]), "radius": R,
                    "group_words": stats["group_words"], "mode": stats["mode"], "slots": stats["slots"],
                    "parallelism": "single GPU"},
-        "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "query": query,
+        "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "query": query, "autotune": tuned,
         "run_stats": stats,
     }
     print(json.dumps(line), flush=True)

@@ -249,6 +249,45 @@ cbfs_status cbfs_profile_enable(int32_t enable);
 cbfs_status cbfs_profile_read(int64_t *launches, double *total_ms);
 
 /* ------------------------------------------------------------------------ *
+ * Autotuner for batched launches (Lemma "word_cost" and Theorem
+ * "batchBFScost", Section 3.2: the cost of a search is set by the arcs it
+ * touches times the words per vertex; which packing, direction thresholds
+ * and launch form are fastest depends on the graph).  Coordinate descent
+ * over launch mode, group width (words per vertex), the push/pull
+ * thresholds alpha and gamma, and in persistent mode the number of groups
+ * searched side by side: each candidate runs cbfs_run_batch twice (one
+ * warm-up) on the first sample_clusters clusters of the batch, timed from
+ * host to stream completion, and the fastest is kept.  No knob changes an
+ * output bit, so the choice only affects speed.
+ *
+ * start:      knobs to start from (nullable: library defaults); fields the
+ *             search does not touch are kept.
+ * sample_clusters: 0 = min(C, 16).
+ * dist/masks/cluster_status: device outputs for at least sample_clusters
+ *             clusters (the batch's own output buffers may be passed; the
+ *             first clusters' outputs are overwritten by the trials).
+ * workspace:  device memory; a candidate whose workspace does not fit is
+ *             skipped (reported with ms < 0).  cbfs_autotune_workspace_size
+ *             gives the size that fits every candidate.
+ * best:       receives the fastest knobs.
+ * trials:     nullable host array of max_trials entries receiving every
+ *             candidate tried, in order; *num_trials receives the count.
+ * The call synchronises the stream.  Errors: those of cbfs_run_batch,
+ * returned from the first candidate that fails.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    cbfs_tuning tuning;
+    float ms;               /* wall time of the timed run; < 0 if skipped */
+    int32_t mode;           /* the mode the run used (CBFS_MODE_HOST_LOOP or _PERSISTENT) */
+} cbfs_trial;
+
+size_t cbfs_autotune_workspace_size(const cbfs_csr *g, const cbfs_batch *b, int32_t sample_clusters);
+cbfs_status cbfs_autotune(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *start,
+                          int32_t sample_clusters, uint32_t *dist, uint64_t *masks, int32_t *cluster_status,
+                          void *workspace, size_t workspace_bytes, void *stream, cbfs_tuning *best,
+                          cbfs_trial *trials, int32_t max_trials, int32_t *num_trials);
+
+/* ------------------------------------------------------------------------ *
  * Landmark-labeling queries over cluster labels (Section 4.2; Algorithm
  * "Framework of Landmark Labeling", Query).  query(s, t) = min over clusters c
  * and sources x of c of d(x, s) + d(x, t); per cluster this is found from the

@@ -21,7 +21,7 @@ SYMBOLS = [
     "cbfs_status_string", "cbfs_last_error", "cbfs_build_csr", "cbfs_top_degree",
     "cbfs_select_clusters", "cbfs_run_batch_workspace_size", "cbfs_run_batch",
     "cbfs_last_run_stats", "cbfs_profile_enable", "cbfs_profile_read",
-    "cbfs_labels_pack", "cbfs_query_batch",
+    "cbfs_labels_pack", "cbfs_query_batch", "cbfs_autotune_workspace_size", "cbfs_autotune",
 ]
 KERNEL_KINDS = ["tiles", "init", "seed", "push", "pull", "finalize", "persistent", "labels", "query"]
 
@@ -52,6 +52,10 @@ class _Tuning(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("gamma", ctypes.c_float)]
 
 
+class _Trial(ctypes.Structure):
+    _fields_ = [("tuning", _Tuning), ("ms", ctypes.c_float), ("mode", ctypes.c_int32)]
+
+
 class _RunStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "groups", "group_words", "slots", "mode", "rounds", "push_rounds", "pull_rounds",
@@ -76,6 +80,11 @@ class Tuning:
     blocks_per_cu: int = 0
     schedule: int = 0
     gamma: float = 0.0
+
+    @classmethod
+    def _from_c(cls, t: _Tuning) -> "Tuning":
+        return cls(t.mode, t.group_words, t.concurrent_groups, t.block_size, t.alpha, t.beta, t.force_pull,
+                   t.blocks_per_cu, t.schedule, t.gamma)
 
     def _c(self) -> _Tuning:
         return _Tuning(self.mode, self.group_words, self.concurrent_groups, self.block_size,
@@ -119,6 +128,10 @@ def load():
     lib.cbfs_labels_pack.restype = i32
     lib.cbfs_query_batch.argtypes = [P, i64, P, P, P, P]
     lib.cbfs_query_batch.restype = i32
+    lib.cbfs_autotune_workspace_size.argtypes = [P, P, i32]
+    lib.cbfs_autotune_workspace_size.restype = sz
+    lib.cbfs_autotune.argtypes = [P, P, P, i32, P, P, P, P, sz, P, P, P, i32, P]
+    lib.cbfs_autotune.restype = i32
     _lib = lib
     return lib
 
@@ -257,6 +270,34 @@ def run_batch(row_ptr_d, col_d, cluster_ptr, sources, R: int, tuning: Tuning | N
                             workspace.numel(), _stream_ptr(stream))
     _check(rc, "cbfs_run_batch")
     return dist, masks, status
+
+
+def autotune(row_ptr_d, col_d, cluster_ptr, sources, R: int, start: Tuning | None = None,
+             sample_clusters: int = 0, stream=None, max_trials: int = 64):
+    """``cbfs_autotune``: returns (best Tuning, [(Tuning, ms, mode) for every trial])."""
+    torch = _torch()
+    lib = load()
+    g, b, t, cptr, srcs = _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, start)
+    C = cptr.size - 1
+    S = min(C, sample_clusters if sample_clusters > 0 else 16)
+    n = row_ptr_d.numel() - 1
+    dev = row_ptr_d.device
+    W = words_for(cptr[: S + 1]) if S >= 1 else 1
+    dist = torch.empty((max(S, 1), n), dtype=torch.int32, device=dev)
+    masks = torch.empty((max(S, 1), 2 * R + 1, n, W), dtype=torch.int64, device=dev)
+    status = torch.empty(max(S, 1), dtype=torch.int32, device=dev)
+    need = max(1, int(lib.cbfs_autotune_workspace_size(ctypes.byref(g), ctypes.byref(b), int(sample_clusters))))
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    best = _Tuning()
+    trials = (_Trial * max_trials)()
+    count = ctypes.c_int32(0)
+    rc = lib.cbfs_autotune(ctypes.byref(g), ctypes.byref(b), ctypes.byref(t) if t is not None else None,
+                           int(sample_clusters), _dptr(dist), _dptr(masks), _dptr(status), _dptr(ws), ws.numel(),
+                           _stream_ptr(stream), ctypes.byref(best), trials, max_trials, ctypes.byref(count))
+    _check(rc, "cbfs_autotune")
+    out = [(Tuning._from_c(trials[i].tuning), float(trials[i].ms), int(trials[i].mode))
+           for i in range(min(count.value, max_trials))]
+    return Tuning._from_c(best), out
 
 
 def labels_pack(dist, masks, R: int, stream=None):

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -542,5 +543,146 @@ extern "C" cbfs_status cbfs_profile_read(int64_t *launches, double *total_ms)
         launches[k] = g_prof_launches[k];
         total_ms[k] = g_prof_ms[k];
     }
+    return CBFS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: coordinate descent over the launch knobs on a sample of the
+// batch (the first clusters), each candidate timed from host to stream
+// completion after one warm-up run.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Tuner {
+    const cbfs_csr *g;
+    cbfs_batch sample;
+    uint32_t *dist;
+    uint64_t *masks;
+    int32_t *status;
+    void *ws;
+    size_t ws_bytes;
+    hipStream_t st;
+    cbfs_trial *out;
+    int32_t max_out;
+    int32_t count = 0;
+    std::vector<cbfs_tuning> seen;
+    cbfs_tuning best{};
+    float best_ms = -1.f;
+
+    static bool same(const cbfs_tuning &a, const cbfs_tuning &b) { return std::memcmp(&a, &b, sizeof a) == 0; }
+
+    // returns CBFS_OK unless a run failed
+    cbfs_status eval(const cbfs_tuning &t)
+    {
+        for (const auto &x : seen)
+            if (same(x, t)) return CBFS_OK;
+        seen.push_back(t);
+        Plan p;
+        float ms = -1.f;
+        int32_t mode = 0;
+        if (make_plan(g, &sample, &t, p, false) == CBFS_OK && p.total <= ws_bytes) {
+            mode = p.mode;
+            hipError_t e;
+            cbfs_status rc = cbfs_run_batch(g, &sample, &t, dist, masks, status, ws, ws_bytes, st);
+            if (rc != CBFS_OK) return rc;
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail("autotune sync", e);
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = cbfs_run_batch(g, &sample, &t, dist, masks, status, ws, ws_bytes, st);
+            if (rc != CBFS_OK) return rc;
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail("autotune sync", e);
+            ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (best_ms < 0.f || ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+        if (out && count < max_out) out[count] = cbfs_trial{t, ms, mode};
+        count++;
+        return CBFS_OK;
+    }
+};
+
+cbfs_batch sample_of(const cbfs_batch *b, int32_t sample_clusters)
+{
+    cbfs_batch s = *b;
+    int32_t S = sample_clusters > 0 ? sample_clusters : 16;
+    if (S > b->num_clusters) S = b->num_clusters;
+    s.num_clusters = S;
+    return s;
+}
+
+const int32_t kTuneWords[] = {1, 2, 4, 8};
+const int32_t kTuneSlots[] = {4, 8, 16, 32, 64};
+
+}  // namespace
+
+extern "C" size_t cbfs_autotune_workspace_size(const cbfs_csr *g, const cbfs_batch *b, int32_t sample_clusters)
+{
+    if (!g || !b || b->num_clusters < 1 || !b->cluster_ptr) return 0;
+    const cbfs_batch sb = sample_of(b, sample_clusters);
+    size_t mx = 0;
+    for (int32_t mode : {CBFS_MODE_HOST_LOOP, CBFS_MODE_PERSISTENT})
+        for (int32_t w : kTuneWords)
+            for (int32_t sl : kTuneSlots) {
+                cbfs_tuning t{};
+                t.mode = mode;
+                t.group_words = w;
+                t.concurrent_groups = sl;
+                Plan p;
+                if (make_plan(g, &sb, &t, p, false) == CBFS_OK) mx = std::max(mx, p.total);
+            }
+    return mx;
+}
+
+extern "C" cbfs_status cbfs_autotune(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *start,
+                                     int32_t sample_clusters, uint32_t *dist, uint64_t *masks,
+                                     int32_t *cluster_status, void *workspace, size_t workspace_bytes,
+                                     void *stream, cbfs_tuning *best, cbfs_trial *trials, int32_t max_trials,
+                                     int32_t *num_trials)
+{
+    g_last_error.clear();
+    if (!g || !b || !best || !dist || !masks || !cluster_status || !workspace)
+        return fail(CBFS_E_ARG, "cbfs_autotune: null argument");
+    if (sample_clusters < 0) return fail(CBFS_E_ARG, "cbfs_autotune: sample_clusters < 0");
+    if (trials && max_trials < 0) return fail(CBFS_E_ARG, "cbfs_autotune: max_trials < 0");
+    Plan p0;
+    cbfs_status rc = make_plan(g, b, start, p0, true);  // validates the whole batch once
+    if (rc != CBFS_OK) return rc;
+    Tuner tu{g, sample_of(b, sample_clusters), dist, masks, cluster_status, workspace, workspace_bytes,
+             (hipStream_t)stream, trials, trials ? max_trials : 0};
+    cbfs_tuning cur{};
+    if (start) cur = *start;
+    const bool sparse = g->m < 8 * g->n;
+    auto step = [&](auto &&mutate, const auto &values) -> cbfs_status {
+        const cbfs_tuning base = tu.best_ms >= 0.f ? tu.best : cur;
+        for (const auto &v : values) {
+            cbfs_tuning t = base;
+            mutate(t, v);
+            if (cbfs_status r = tu.eval(t); r != CBFS_OK) return r;
+        }
+        return CBFS_OK;
+    };
+    if ((rc = tu.eval(cur)) != CBFS_OK) return rc;
+    // launch mode (the host loop costs a round trip per round: not tried on
+    // sparse graphs, which run thousands of rounds)
+    if (!sparse) {
+        const int32_t modes[] = {CBFS_MODE_HOST_LOOP, CBFS_MODE_PERSISTENT};
+        if ((rc = step([](cbfs_tuning &t, int32_t v) { t.mode = v; }, modes)) != CBFS_OK) return rc;
+    }
+    std::vector<int32_t> words;  // packings valid for the whole batch's clusters
+    for (int32_t w : kTuneWords)
+        if (valid_w(w, p0.WC)) words.push_back(w);
+    if ((rc = step([](cbfs_tuning &t, int32_t v) { t.group_words = v; }, words)) != CBFS_OK) return rc;
+    const float alphas[] = {5.f, 15.f, 45.f};
+    if ((rc = step([](cbfs_tuning &t, float v) { t.alpha = v; }, alphas)) != CBFS_OK) return rc;
+    const float gammas[] = {0.25f, 0.5f, -1.f};
+    if ((rc = step([](cbfs_tuning &t, float v) { t.gamma = v; }, gammas)) != CBFS_OK) return rc;
+    Plan pb;
+    if (make_plan(g, &tu.sample, &tu.best, pb, false) == CBFS_OK && pb.mode == CBFS_MODE_PERSISTENT)
+        if ((rc = step([](cbfs_tuning &t, int32_t v) { t.concurrent_groups = v; }, kTuneSlots)) != CBFS_OK)
+            return rc;
+    if (tu.best_ms < 0.f) return fail(CBFS_E_WORKSPACE, "cbfs_autotune: no candidate fits the workspace");
+    *best = tu.best;
+    if (num_trials) *num_trials = tu.count;
     return CBFS_OK;
 }

@@ -190,3 +190,22 @@ def test_parity_workloads_small(name, mode):
     assert (ref[2] == 0).all()
     stats = P.last_run_stats()
     assert stats["device_error"] == 0 and stats["rounds"] > 0
+
+
+def test_autotuned_knobs_keep_every_bit():
+    """The autotuner's choice, and every trial it timed, reproduce the oracle."""
+    import paper_2410_17226_amd as P
+    torch = _torch()
+    cfg, (ours, ref_in) = workload_inputs("rmat16_batch")
+    rp, col, cp, src = ours
+    rp_d, col_d = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    best, trials = P.autotune(rp_d, col_d, cp, src, cfg["R"], sample_clusters=8)
+    timed = [t for t in trials if t[1] >= 0]
+    assert len(timed) >= 5
+    assert min(ms for _, ms, _ in timed) == min(ms for t, ms, _ in timed if t == best)
+    ref = oracle.cbfs(*ref_in, R=cfg["R"])
+    assert_same(gpu_cbfs(rp, col, cp, src, cfg["R"], best), ref, f"autotuned {best}")
+    for t, ms, mode in trials[:6]:
+        if ms >= 0:
+            assert_same(gpu_cbfs(rp, col, cp, src, cfg["R"], t), ref, f"trial {t}")
+

@@ -146,3 +146,29 @@ def test_workspace_size_monotone():
     assert size(1000, 5000, 64, 4, P.Tuning(group_words=1, concurrent_groups=4)) > \
         size(1000, 5000, 64, 4, P.Tuning(group_words=1, **one))
     assert size(1000, 5000, 300, 1) == 0  # invalid: more than 256 sources
+
+
+def test_autotune_argument_errors_before_launch():
+    """Null outputs or a bad sample size are rejected on the host (no kernel runs)."""
+    lib = P.load()
+    rp = np.array([0, 1, 2], np.int32)
+    col = np.array([1, 0], np.int32)
+    g = B._Csr(2, 2, rp.ctypes.data, col.ctypes.data)   # host pointers: never dereferenced here
+    cp = np.array([0, 1], np.int32)
+    src = np.array([0], np.int32)
+    b = B._Batch(1, cp.ctypes.data, src.ctypes.data, 1)
+    best = B._Tuning()
+    rc = lib.cbfs_autotune(ctypes.byref(g), ctypes.byref(b), None, 0, None, None, None, None, 0, None,
+                           ctypes.byref(best), None, 0, None)
+    assert rc == -1
+    buf = ctypes.c_void_p(1)
+    rc = lib.cbfs_autotune(ctypes.byref(g), ctypes.byref(b), None, -1, buf, buf, buf, buf, 0, None,
+                           ctypes.byref(best), None, 0, None)
+    assert rc == -1
+    bad = np.array([0, 0], np.int32)     # empty cluster
+    b2 = B._Batch(1, bad.ctypes.data, src.ctypes.data, 1)
+    rc = lib.cbfs_autotune(ctypes.byref(g), ctypes.byref(b2), None, 0, buf, buf, buf, buf, 0, None,
+                           ctypes.byref(best), None, 0, None)
+    assert rc == -4  # CBFS_E_TOO_MANY_SOURCES
+    assert lib.cbfs_autotune_workspace_size(ctypes.byref(g), ctypes.byref(b), 0) > 0
+
