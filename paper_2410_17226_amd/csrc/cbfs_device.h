@@ -128,6 +128,19 @@ __device__ __forceinline__ void store_words(uint64_t *p, const uint64_t (&x)[W])
 
 __device__ __forceinline__ int pieces_of(int deg) { return deg > PIECE ? (deg + PIECE - 1) / PIECE : 1; }
 
+// Queue entries per push block: about PUSH_BLOCK_ARCS arcs per block, so that
+// a frontier of a few hub vertices (pieces of PIECE arcs) still spreads over
+// many blocks; a power of two in [8, BLOCK].
+constexpr int64_t PUSH_BLOCK_ARCS = 4096;
+__host__ __device__ inline int32_t push_entries_per_block(int64_t pieces, int64_t degsum)
+{
+    if (pieces <= 0 || degsum <= 0) return BLOCK;
+    int64_t want = PUSH_BLOCK_ARCS * pieces / degsum;
+    int32_t e = BLOCK;
+    while (e > 8 && e > want) e >>= 1;
+    return e;
+}
+
 // ---------------------------------------------------------------------------
 // Output encoding for one cluster at vertex v, round i (the vertex phase's
 // "S_u[i - Delta_u] <- S_new" of Algorithm "Cluster-BFS search from S",

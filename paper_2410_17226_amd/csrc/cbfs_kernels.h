@@ -44,7 +44,7 @@ hipError_t launch_init(int W, const SlotArgs &s, int64_t n, const GroupDesc &g, 
 hipError_t launch_seed(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                        const int32_t *sources, const int32_t *cluster_ptr, hipStream_t st);
 hipError_t launch_push(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                       const OutArgs &o, int32_t round, int64_t nq, hipStream_t st);
+                       const OutArgs &o, int32_t round, int64_t nq, int64_t degsum, hipStream_t st);
 hipError_t launch_pull(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                        const OutArgs &o, int32_t round, int32_t test_frontier, hipStream_t st);
 hipError_t launch_finalize(int W, int WC, const SlotArgs &s, int64_t n, const GroupDesc &g, const OutArgs &o,

@@ -55,11 +55,11 @@ __global__ __launch_bounds__(BLOCK) void k_seed(SlotArgs s, GraphArgs gr, GroupD
 
 template <int W, int WC>
 __global__ __launch_bounds__(BLOCK) void k_push(SlotArgs s, GraphArgs gr, GroupDesc g, OutArgs o, int32_t round,
-                                                int64_t nq)
+                                                int64_t nq, int32_t epb)
 {
     __shared__ PushSmem<W> sm;
     clear_ahead_part(s, round, (int64_t)blockIdx.x * BLOCK + threadIdx.x, (int64_t)gridDim.x * BLOCK);
-    push_chunk<W, WC>(sm, s, gr, g, o, round, nq, blockIdx.x);
+    push_chunk<W, WC>(sm, s, gr, g, o, round, nq, blockIdx.x, epb);
 }
 
 template <int W, int WC>
@@ -219,6 +219,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
     __shared__ int32_t s_sparse[MAX_SLOTS];
     __shared__ int64_t s_work[MAX_SLOTS];   // push chunks or pull tiles
     __shared__ int64_t s_nq[MAX_SLOTS];     // pieces in F_i
+    __shared__ int32_t s_epb[MAX_SLOTS];    // queue entries per push chunk
     __shared__ int64_t s_nprev[MAX_SLOTS];  // pieces in F_{i-1}
     __shared__ int64_t s_pref[MAX_SLOTS + 1];
     __shared__ int tmp[WAVES + 1];
@@ -290,7 +291,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                     if (dense && a.gamma > 0.f && (double)degsum > (double)a.gamma * (double)a.gr.m) dense = 2;
                     else if (dense) dense = 1;
                     s_dense[sl_me] = dense;
-                    work = dense ? a.gr.ntiles : (pieces + BLOCK - 1) / BLOCK;
+                    const int32_t epb = push_entries_per_block(pieces, degsum);
+                    s_epb[sl_me] = epb;
+                    work = dense ? a.gr.ntiles : (pieces + epb - 1) / epb;
                     // bitmap words of F_{i-1} to clear: sparse through its queue
                     // when that is cheaper than a dense pass
                     const bool sparse = nprev * 4 < sd.nwords;
@@ -368,7 +371,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                         pull_tile<W, WC>(sm.pull, s_slot, a.gr, s_group, a.o, round, (int32_t)local,
                                          s_dense[sl] == 1);
                     } else {
-                        push_chunk<W, WC>(sm.push, s_slot, a.gr, s_group, a.o, round, s_nq[sl], local);
+                        push_chunk<W, WC>(sm.push, s_slot, a.gr, s_group, a.o, round, s_nq[sl], local, s_epb[sl]);
                     }
                 }
             }
@@ -426,11 +429,12 @@ hipError_t launch_seed(int W, int WC, const SlotArgs &s, const GraphArgs &gr, co
 }
 
 hipError_t launch_push(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                       const OutArgs &o, int32_t round, int64_t nq, hipStream_t st)
+                       const OutArgs &o, int32_t round, int64_t nq, int64_t degsum, hipStream_t st)
 {
-    int64_t work = (nq + BLOCK - 1) / BLOCK;
+    const int32_t epb = push_entries_per_block(nq, degsum);
+    int64_t work = (nq + epb - 1) / epb;
     int64_t blocks = std::max<int64_t>(work, clear_blocks(s.nwords));
-    CBFS_DISPATCH(W, WC, (k_push<W, WC><<<(unsigned)blocks, BLOCK, 0, st>>>(s, gr, g, o, round, nq)));
+    CBFS_DISPATCH(W, WC, (k_push<W, WC><<<(unsigned)blocks, BLOCK, 0, st>>>(s, gr, g, o, round, nq, epb)));
     return hipGetLastError();
 }
 

@@ -111,8 +111,9 @@ __device__ void seed_block(Stager<STAGE_CAP> &st, const SlotArgs &s, const Graph
 }
 
 // ---------------------------------------------------------------------------
-// Round i, push direction (EdgeMap-Sparse), one chunk of BLOCK queue entries
-// (pieces of <= PIECE arcs): the vertex phase for first pieces, then the
+// Round i, push direction (EdgeMap-Sparse), one chunk of epb <= BLOCK queue
+// entries (pieces of <= PIECE arcs; epb from push_entries_per_block, so a
+// chunk holds about PUSH_BLOCK_ARCS arcs): the vertex phase for first pieces, then the
 // chunk's arcs spread evenly over the block (block scan + binary search of
 // each arc's owner).  Per arc (u, v): x = Seen_i(u) \ Seen_i(v); if not empty,
 // 64-bit atomic OR into nxt(v) and claim v (the Fetch_And_Or and
@@ -120,9 +121,9 @@ __device__ void seed_block(Stager<STAGE_CAP> &st, const SlotArgs &s, const Graph
 // ---------------------------------------------------------------------------
 template <int W, int WC>
 __device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                           const OutArgs &o, int32_t round, int64_t nq, int64_t chunk)
+                           const OutArgs &o, int32_t round, int64_t nq, int64_t chunk, int32_t epb)
 {
-    const int64_t first = chunk * BLOCK;
+    const int64_t first = chunk * epb;
     if (first >= nq) return;  // block-uniform
     __syncthreads();
     stager_init(sm.st);
@@ -134,7 +135,7 @@ __device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &
 
     int cnt = 0;
     const int64_t idx = first + threadIdx.x;
-    if (idx < nq) {
+    if ((int32_t)threadIdx.x < epb && idx < nq) {
         const int64_t e = q_buf(s, round)[idx];
         const int32_t u = (int32_t)(e & 0xffffffff);
         const int32_t p = (int32_t)(e >> 32);

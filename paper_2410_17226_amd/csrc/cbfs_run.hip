@@ -354,7 +354,7 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
             // nothing new, Section 3.2, and the test would pass for most arcs)
             const int32_t test = !(p.gamma > 0.0f && (double)degsum > (double)p.gamma * (double)p.m);
             if (dense) e = PROF(CBFS_KERNEL_PULL, st, launch_pull(p.W, p.WC, s, gr, gd, o, round, test, st));
-            else e = PROF(CBFS_KERNEL_PUSH, st, launch_push(p.W, p.WC, s, gr, gd, o, round, pieces, st));
+            else e = PROF(CBFS_KERNEL_PUSH, st, launch_push(p.W, p.WC, s, gr, gd, o, round, pieces, degsum, st));
             if (e != hipSuccess) return hip_fail(dense ? "pull" : "push", e);
         }
         if ((e = PROF(CBFS_KERNEL_FINALIZE, st, launch_finalize(p.W, p.WC, s, p.n, gd, o, st))) != hipSuccess)
