@@ -39,7 +39,9 @@ constexpr int TILE_ITEMS = 8192;    // merge-path items (rows + arcs) per pull b
 constexpr int IPT = TILE_ITEMS / BLOCK;
 static_assert(TILE_ITEMS + 2 <= 65535, "pull tiles stage row ends as 16-bit offsets");
 constexpr int PULL_CLAIM_WORDS = TILE_ITEMS / 64 + 2;  // bitmap words spanned by a tile's rows
+constexpr int PULL_ROW_WORDS = (TILE_ITEMS + 1 + 63) / 64;  // one bit per row of a tile
 static_assert(PULL_CLAIM_WORDS <= BLOCK, "one claimed word per thread at a pull tile's flush");
+enum { PULL_WALK = 0, PULL_WAVE = 1 };  // forms of the pull round
 constexpr int STAGE_CAP = 1024;     // LDS frontier staging capacity per push/seed block
 constexpr int MAX_W = 8;            // max words per vertex in a group
 constexpr uint32_t UNREACHED = 0xFFFFFFFFu;
@@ -299,6 +301,35 @@ __device__ __forceinline__ int block_exclusive_scan(int x, int *tmp /*[WAVES+1]*
     __syncthreads();
     *total = tmp[WAVES];
     const int r = v - x + tmp[wid];
+    __syncthreads();
+    return r;
+}
+
+// Exclusive block max-scan of one non-negative int per thread (0 for the
+// first thread).
+__device__ __forceinline__ int block_exclusive_max(int x, int *tmp /*[WAVES+1]*/)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(v, d, 64);
+        if (lane >= d) v = v > y ? v : y;
+    }
+    if (lane == 63) tmp[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < WAVES; w++) {
+            int t = tmp[w];
+            tmp[w] = acc;
+            acc = acc > t ? acc : t;
+        }
+    }
+    __syncthreads();
+    int prev = __shfl_up(v, 1, 64);
+    if (lane == 0) prev = 0;
+    const int r = prev > tmp[wid] ? prev : tmp[wid];
     __syncthreads();
     return r;
 }

@@ -46,7 +46,7 @@ hipError_t launch_seed(int W, int WC, const SlotArgs &s, const GraphArgs &gr, co
 hipError_t launch_push(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                        const OutArgs &o, int32_t round, int64_t nq, int64_t degsum, hipStream_t st);
 hipError_t launch_pull(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                       const OutArgs &o, int32_t round, int32_t test_frontier, hipStream_t st);
+                       const OutArgs &o, int32_t round, int32_t form, hipStream_t st);
 hipError_t launch_finalize(int W, int WC, const SlotArgs &s, int64_t n, const GroupDesc &g, const OutArgs &o,
                            hipStream_t st);
 // Blocks of the persistent kernel on the current device: per_cu per compute

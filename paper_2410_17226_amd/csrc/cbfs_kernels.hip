@@ -64,11 +64,11 @@ __global__ __launch_bounds__(BLOCK) void k_push(SlotArgs s, GraphArgs gr, GroupD
 
 template <int W, int WC>
 __global__ __launch_bounds__(BLOCK) void k_pull(SlotArgs s, GraphArgs gr, GroupDesc g, OutArgs o, int32_t round,
-                                               int32_t test_frontier)
+                                               int32_t form)
 {
     __shared__ PullSmem<W> sm;
     clear_ahead_part(s, round, (int64_t)blockIdx.x * BLOCK + threadIdx.x, (int64_t)gridDim.x * BLOCK);
-    pull_tile<W, WC>(sm, s, gr, g, o, round, blockIdx.x, test_frontier != 0);
+    pull_tile<W, WC>(sm, s, gr, g, o, round, blockIdx.x, form);
 }
 
 template <int W, int WC>
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                         clear_item(s_slot, round, s_sparse[sl] != 0, s_nprev[sl], local - s_work[sl]);
                     } else if (s_dense[sl]) {
                         pull_tile<W, WC>(sm.pull, s_slot, a.gr, s_group, a.o, round, (int32_t)local,
-                                         s_dense[sl] == 1);
+                                         s_dense[sl] == 2 ? PULL_WAVE : PULL_WALK);
                     } else {
                         push_chunk<W, WC>(sm.push, s_slot, a.gr, s_group, a.o, round, s_nq[sl], local, s_epb[sl]);
                     }
@@ -439,9 +439,9 @@ hipError_t launch_push(int W, int WC, const SlotArgs &s, const GraphArgs &gr, co
 }
 
 hipError_t launch_pull(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                       const OutArgs &o, int32_t round, int32_t test_frontier, hipStream_t st)
+                       const OutArgs &o, int32_t round, int32_t form, hipStream_t st)
 {
-    CBFS_DISPATCH(W, WC, (k_pull<W, WC><<<(unsigned)gr.ntiles, BLOCK, 0, st>>>(s, gr, g, o, round, test_frontier)));
+    CBFS_DISPATCH(W, WC, (k_pull<W, WC><<<(unsigned)gr.ntiles, BLOCK, 0, st>>>(s, gr, g, o, round, form)));
     return hipGetLastError();
 }
 

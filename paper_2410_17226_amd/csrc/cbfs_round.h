@@ -19,12 +19,22 @@ struct PushSmem {
 
 template <int W>
 struct PullSmem {
-    uint64_t part[BLOCK][W];                 // partial sets of rows shared by threads, by first thread
-    uint64_t claimed[PULL_CLAIM_WORDS];      // F_{i+1} bits of the tile's rows, from word tile_row >> 6
     uint16_t rend[TILE_ITEMS + 2];           // row_end of the tile's rows minus tile_edge (clamped)
+    uint64_t claimed[PULL_CLAIM_WORDS];      // F_{i+1} bits of the tile's rows, from word tile_row >> 6
     int tmp[WAVES + 1];
     unsigned long long degsum;
     long long base;
+    union {
+        uint64_t part[BLOCK][W];             // walk: partial sets of rows shared by threads, by first thread
+        struct {
+            uint16_t arow[TILE_ITEMS];       // row of each of the tile's arcs, minus tile_row
+            uint64_t fin[PULL_ROW_WORDS];    // rows whose set is complete (bit: row - tile_row)
+            uint64_t stored[PULL_ROW_WORDS]; // local rows whose nxt the arc phase stored
+            uint64_t out_acc[WAVES][W];      // a wave's share of the row still open at its range end
+            uint64_t pend_acc[WAVES][W];     // a wave's share of a row it closes that began earlier
+            int32_t out_row[WAVES], pend_row[WAVES];
+        } wv;                                // wave form
+    };
 };
 
 template <int W>
@@ -185,37 +195,61 @@ __device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &
 
 // ---------------------------------------------------------------------------
 // Round i, pull direction (EdgeMap-Dense), one merge-path tile of TILE_ITEMS
-// items (arcs and row ends) of the CSR.  The tile's row ends are first staged
-// in LDS (as offsets from the tile's first arc), so that each thread finds its
-// merge-path start and walks its rows without global row-pointer loads.  Each
-// thread then walks IPT consecutive items row segment by row segment.  For a
-// row v it loads Seen_i(v) once (a finished row, holding every source, is
-// skipped: EdgeMap's Cond_F), then processes its arcs in batches: the frontier
-// bits of all neighbours in the batch, then Seen_i(u) of all of them, are
-// requested together (unconditional loads with a select, so the loads
-// overlap), and the new bits are OR-ed into a register accumulator; the row
-// stops once the accumulator completes the set (EdgeMap-Dense's break).
-// Without test_frontier every neighbour's set is OR-ed: a neighbour outside
-// F_i has Seen_i(u) = Seen_{i-1}(u), already inside Seen_i(v), so this only
-// saves the bitmap lookups when F_i holds most of the arcs.
+// items (arcs and row ends) of the CSR: rows [tile_row, next tile_row) end in
+// the tile, and its arcs are [tile_edge, next tile_edge).  The tile's row ends
+// are staged in LDS (offsets from its first arc).
 //
-// Every row has one owner, the thread that consumes its end item.  For a row
-// whose arcs and end all lie in this tile (a local row) the partial sets of
-// the threads on it meet in LDS (slot of the row's first thread), and the
-// owner writes nxt(v) = Seen_i(v) | new with a plain store and claims v in an
-// LDS bitmap of the tile's rows.  Only the (at most two) rows that cross the
-// tile's edges merge into nxt and the frontier bitmap with global atomics; a
-// claim they win joins the LDS bitmap.  Then the vertex phase runs for the
-// rows whose end item is in the tile and that are in F_i, one row per thread,
-// so its loads and stores are coalesced.  Finally the claimed words go to the
-// frontier bitmap (plain stores where a word only holds local rows of this
-// tile) and the claimed rows, expanded into their pieces, to the F_{i+1}
-// queue at offsets from one block scan.
+// Every row has one owner in the tile that holds its end item.  A row whose
+// arcs and end all lie in this tile (a local row) gets nxt(v) = Seen_i(v) |
+// new by a plain store and its claim in an LDS bitmap of the tile's rows; the
+// (at most two) rows that cross the tile's edges merge into nxt and the
+// frontier bitmap with global atomics.  After the arc phase the vertex phase
+// runs for the rows whose end item is in the tile and that are in F_i, one
+// row per thread (coalesced).  Finally the claimed words go to the frontier
+// bitmap (plain stores where a word only holds local rows) and the claimed
+// rows, expanded into their pieces, to the F_{i+1} queue at offsets from one
+// block scan.
+//
+// Two forms of the arc phase, chosen per round:
+//   PULL_WALK  each thread walks IPT consecutive items row segment by row
+//              segment; per row it skips a complete set (EdgeMap's Cond_F),
+//              gathers Seen_i(u) only for neighbours u in F_i (a neighbour
+//              outside F_i has Seen_i(u) = Seen_{i-1}(u), already inside
+//              Seen_i(v)) and stops once the set is complete (EdgeMap-Dense's
+//              break).  Neighbour ids and frontier words are fetched one and
+//              two batches ahead.  Partial sets of rows that span threads meet
+//              in LDS.  Best when many rows are complete or F_i is small.
+//   PULL_WAVE  each wave takes a contiguous quarter of the tile's arcs, 64
+//              consecutive arcs per step (coalesced ids; a row's sorted
+//              neighbours share cache lines) and gathers Seen_i(u) for every
+//              neighbour of an incomplete row; a segmented OR-scan combines
+//              each row's lanes.  Best when F_i holds most arcs and few rows
+//              are complete (the first dense rounds).
 // ---------------------------------------------------------------------------
-template <int W>
-constexpr int pull_batch()
+struct PullTile {
+    int32_t r0, e0, r1, e1;      // first row / arc of this tile and of the next
+    int32_t tile_rows, tile_edges, tile_items;
+    int32_t start_r0, end_r1;    // row_ptr[r0] (may lie before e0), row_end of r1
+    int32_t loc_lo;              // local rows: [loc_lo, r1)
+    int32_t wbase, nclaim;       // claimed bitmap words [wbase, wbase + nclaim)
+};
+
+__device__ __forceinline__ PullTile pull_coords(const GraphArgs &gr, int32_t t)
 {
-    return W <= 2 ? 8 : (W <= 4 ? 4 : 1);
+    PullTile T;
+    T.r0 = gr.tile_row[t];
+    T.e0 = gr.tile_edge[t];
+    T.r1 = gr.tile_row[t + 1];
+    T.e1 = gr.tile_edge[t + 1];
+    T.tile_rows = T.r1 - T.r0;
+    T.tile_edges = T.e1 - T.e0;
+    T.tile_items = T.tile_rows + T.tile_edges;
+    T.start_r0 = gr.row_ptr[T.r0];
+    T.end_r1 = (int64_t)T.r1 < gr.n ? gr.row_ptr[T.r1 + 1] : T.e1;
+    T.loc_lo = T.start_r0 >= T.e0 ? T.r0 : T.r0 + 1;
+    T.wbase = T.r0 >> 6;
+    T.nclaim = (T.r1 >> 6) - T.wbase + 1;
+    return T;
 }
 
 // OR x (non-empty, bits v lacked in round i) into nxt(v) for a row whose arcs
@@ -232,55 +266,60 @@ __device__ __forceinline__ bool merge_global(uint64_t *nxt, uint64_t *bits_next,
     return !(old & bit);
 }
 
+template <int W>
+__device__ __forceinline__ void pull_claim(PullSmem<W> &sm, const PullTile &T, int32_t v)
+{
+    atomicOr(reinterpret_cast<unsigned long long *>(&sm.claimed[(v >> 6) - T.wbase]), 1ull << (v & 63));
+}
+
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t x, int d)
+{
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 64);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int W>
+constexpr int pull_batch()
+{
+    return W <= 2 ? 8 : (W <= 4 ? 4 : 1);
+}
+
+// PULL_WALK arc phase and vertex phase (see above).
 template <int W, int WC>
-__device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                          const OutArgs &o, int32_t round, int32_t t, bool test_frontier)
+__device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
+                          const OutArgs &o, int32_t round, const PullTile &T)
 {
     constexpr int NB = pull_batch<W>();
     const uint64_t *cur = cur_buf(s, round);
     uint64_t *nxt = nxt_buf(s, round);
     const uint64_t *bits_cur = bits_buf(s, round % 3);
     uint64_t *bits_next = bits_buf(s, (round + 1) % 3);
-
-    const int32_t r0 = gr.tile_row[t], e0 = gr.tile_edge[t];
-    const int32_t r1 = gr.tile_row[t + 1], e1 = gr.tile_edge[t + 1];
-    // merge-path coordinates inside the tile: arc e of row r is item
-    // (r - r0) + (e - e0); the end item of row r is (r - r0) + (row_end[r] - e0).
-    // Rows r0 .. r1 - 1 end in this tile; row r1 (if it exists) may have arcs
-    // here and end in a later tile.
-    const int32_t tile_rows = r1 - r0, tile_edges = e1 - e0;
-    const int32_t tile_items = tile_rows + tile_edges;
-    const int32_t start_r0 = gr.row_ptr[r0];  // may lie before e0
-    const int32_t end_r1 = (int64_t)r1 < gr.n ? gr.row_ptr[r1 + 1] : e1;
-    // local rows: [loc_lo, r1), those whose first arc is in this tile
-    const int32_t loc_lo = start_r0 >= e0 ? r0 : r0 + 1;
-    const int32_t wbase = r0 >> 6;
-    const int32_t nclaim = (r1 >> 6) - wbase + 1;
-    __syncthreads();
+    const int32_t r0 = T.r0, e0 = T.e0, r1 = T.r1;
 #pragma unroll
     for (int w = 0; w < W; w++) sm.part[threadIdx.x][w] = 0;
-    for (int32_t k = threadIdx.x; k < nclaim; k += BLOCK) sm.claimed[k] = 0;
-    for (int32_t k = threadIdx.x; k <= tile_rows; k += BLOCK) {
-        const int32_t r = r0 + k;
-        int32_t x = ((int64_t)r < gr.n ? gr.row_ptr[r + 1] : e1) - e0;
-        sm.rend[k] = (uint16_t)(x > tile_edges + 1 ? tile_edges + 1 : x);
-    }
-    if (threadIdx.x == 0) sm.degsum = 0;
     __syncthreads();
     // row_end[r] for a row of the tile (exact for r < r1; past e1 for r1)
     auto rend_of = [&](int32_t r) { return e0 + (int32_t)sm.rend[r - r0]; };
-    auto rstart_of = [&](int32_t r) { return r == r0 ? start_r0 : e0 + (int32_t)sm.rend[r - 1 - r0]; };
+    auto rstart_of = [&](int32_t r) { return r == r0 ? T.start_r0 : e0 + (int32_t)sm.rend[r - 1 - r0]; };
 
     // this thread's merge-path start inside the tile
     int32_t rel = (int32_t)threadIdx.x * IPT;
-    if (rel > tile_items) rel = tile_items;
+    if (rel > T.tile_items) rel = T.tile_items;
     int32_t my_end = ((int32_t)threadIdx.x + 1) * IPT;
-    if (my_end > tile_items) my_end = tile_items;
+    if (my_end > T.tile_items) my_end = T.tile_items;
     const int32_t my_start = rel;
     int32_t row, edge;
     {
-        int32_t lo = rel > tile_edges ? rel - tile_edges : 0;
-        int32_t hi = rel < tile_rows ? rel : tile_rows;
+        int32_t lo = rel > T.tile_edges ? rel - T.tile_edges : 0;
+        int32_t hi = rel < T.tile_rows ? rel : T.tile_rows;
         while (lo < hi) {
             int32_t mid = (lo + hi) >> 1;
             if ((int32_t)sm.rend[mid] <= rel - mid - 1) lo = mid + 1;
@@ -294,9 +333,6 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
 #pragma unroll
     for (int w = 0; w < W; w++) full[w] = g.full[w];
 
-    auto claim_lds = [&](int32_t v) {
-        atomicOr(reinterpret_cast<unsigned long long *>(&sm.claimed[(v >> 6) - wbase]), 1ull << (v & 63));
-    };
     auto finish_local = [&](int32_t v, const uint64_t (&cv)[W], const uint64_t (&acc)[W]) {
         bool any = false;
 #pragma unroll
@@ -308,7 +344,7 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
             for (int w = 0; w < W; w++) nv[w] = cv[w] | acc[w];
             store_words<W>(nxt + (size_t)v * W, nv);
         }
-        if (any) claim_lds(v);
+        if (any) pull_claim(sm, T, v);
     };
 
     // a local row owned here whose first arcs other threads scanned: its own
@@ -320,7 +356,21 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         const int32_t budget = my_end - rel;
         const int32_t seg_end = rend < edge + budget ? rend : edge + budget;
         uint64_t cv[W], acc[W];
+        // software pipeline: the row's own set, the first two batches'
+        // neighbour ids and the first batch's frontier words are requested
+        // together; in the loop, batch k's Seen_i(u) gathers go out with
+        // batch k+1's frontier words and batch k+2's ids, so each batch waits
+        // for its own gathers only
         load_words<W>(cur + (size_t)row * W, cv);
+        int32_t u0[NB], u1[NB];
+        uint64_t b0[NB];
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+            u0[j] = (edge + j < seg_end) ? gr.col[edge + j] : row;
+            u1[j] = (edge + NB + j < seg_end) ? gr.col[edge + NB + j] : row;
+        }
+#pragma unroll
+        for (int j = 0; j < NB; j++) b0[j] = bits_cur[u0[j] >> 6];
         bool fin = true;
 #pragma unroll
         for (int w = 0; w < W; w++) {
@@ -329,27 +379,29 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         }
         for (int32_t e = edge; e < seg_end && !fin; e += NB) {
             int32_t u[NB];
-            bool hit[NB];
+            uint64_t hm[NB];  // all ones for a neighbour whose set counts
 #pragma unroll
-            for (int j = 0; j < NB; j++) u[j] = (e + j < seg_end) ? gr.col[e + j] : row;
-            if (test_frontier) {
-                uint64_t bw[NB];
-#pragma unroll
-                for (int j = 0; j < NB; j++) bw[j] = bits_cur[u[j] >> 6];
-#pragma unroll
-                for (int j = 0; j < NB; j++) hit[j] = ((bw[j] >> (u[j] & 63)) & 1ull) && (e + j < seg_end);
-            } else {
-#pragma unroll
-                for (int j = 0; j < NB; j++) hit[j] = e + j < seg_end;
+            for (int j = 0; j < NB; j++) {
+                const bool hit = (((b0[j] >> (u0[j] & 63)) & 1ull) != 0) && e + j < seg_end;
+                hm[j] = hit ? ~0ull : 0ull;
+                u[j] = hit ? u0[j] : row;  // keep the load in place, its value is masked off
             }
             uint64_t cu[NB][W];
 #pragma unroll
-            for (int j = 0; j < NB; j++) load_words<W>(cur + (size_t)(hit[j] ? u[j] : row) * W, cu[j]);
+            for (int j = 0; j < NB; j++) load_words<W>(cur + (size_t)u[j] * W, cu[j]);
+#pragma unroll
+            for (int j = 0; j < NB; j++) b0[j] = bits_cur[u1[j] >> 6];
+#pragma unroll
+            for (int j = 0; j < NB; j++) {
+                u0[j] = u1[j];
+                u1[j] = (e + 2 * NB + j < seg_end) ? gr.col[e + 2 * NB + j] : row;
+            }
             bool f = true;
 #pragma unroll
             for (int w = 0; w < W; w++) {
 #pragma unroll
-                for (int j = 0; j < NB; j++) acc[w] |= hit[j] ? (cu[j][w] & ~cv[w]) : 0ull;
+                for (int j = 0; j < NB; j++) acc[w] |= cu[j][w] & hm[j];
+                acc[w] &= ~cv[w];
                 f &= (acc[w] | cv[w]) == full[w];
             }
             fin = f;
@@ -364,7 +416,7 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
             bool any = false;
 #pragma unroll
             for (int w = 0; w < W; w++) any |= acc[w] != 0;
-            if (any && merge_global<W>(nxt, bits_next, row, acc)) claim_lds(row);
+            if (any && merge_global<W>(nxt, bits_next, row, acc)) pull_claim(sm, T, row);
         } else if (!owns_end || first_item < my_start) {
             // a local row other threads share: into the slot of its first thread
             uint64_t *slot = sm.part[first_item / IPT];
@@ -393,20 +445,257 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     // vertex phase of the rows whose end item is in this tile
     for (int32_t v = r0 + (int32_t)threadIdx.x; v < r1; v += BLOCK) {
         if (!((bits_cur[v >> 6] >> (v & 63)) & 1ull)) continue;
-        if (v < loc_lo) vertex_phase<W, WC, true>(s, g, o, gr.n, round, v);  // tile-crossing row
+        if (v < T.loc_lo) vertex_phase<W, WC, true>(s, g, o, gr.n, round, v);  // tile-crossing row
         else vertex_phase<W, WC, false>(s, g, o, gr.n, round, v);
     }
     __syncthreads();
+}
+
+// PULL_WAVE arc phase and vertex phase (see above).
+template <int W, int WC>
+__device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
+                          const OutArgs &o, int32_t round, const PullTile &T)
+{
+    const uint64_t *cur = cur_buf(s, round);
+    uint64_t *nxt = nxt_buf(s, round);
+    const uint64_t *bits_cur = bits_buf(s, round % 3);
+    uint64_t *bits_next = bits_buf(s, (round + 1) % 3);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int32_t r0 = T.r0, e0 = T.e0, r1 = T.r1, tile_rows = T.tile_rows, tile_edges = T.tile_edges;
+    const int32_t nrw = (tile_rows + 1 + 63) >> 6;
+    uint64_t full[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) full[w] = g.full[w];
+
+    for (int32_t k = threadIdx.x; k < tile_edges; k += BLOCK) sm.wv.arow[k] = 0;
+    for (int32_t k = threadIdx.x; k < nrw; k += BLOCK) {
+        sm.wv.fin[k] = 0;
+        sm.wv.stored[k] = 0;
+    }
+    if (threadIdx.x < WAVES) {
+        sm.wv.out_row[threadIdx.x] = -1;
+        sm.wv.pend_row[threadIdx.x] = -1;
+    }
+    __syncthreads();
+    // row start offset of row r0 + k (negative for a row begun before the tile)
+    auto rstart_off = [&](int32_t k) { return k == 0 ? T.start_r0 - e0 : (int32_t)sm.rend[k - 1]; };
+    // row starts scattered for the arc -> row map; complete rows marked
+    for (int32_t k = threadIdx.x; k <= tile_rows; k += BLOCK) {
+        const int32_t r = r0 + k;
+        if ((int64_t)r >= gr.n) continue;
+        const int32_t so = rstart_off(k);
+        const int32_t a = so > 0 ? so : 0;
+        const int32_t b = (int32_t)sm.rend[k] < tile_edges ? (int32_t)sm.rend[k] : tile_edges;
+        if (a < b) sm.wv.arow[a] = (uint16_t)k;
+        uint64_t cv[W];
+        load_words<W>(cur + (size_t)r * W, cv);
+        bool f = true;
+#pragma unroll
+        for (int w = 0; w < W; w++) f &= cv[w] == full[w];
+        if (f) atomicOr(reinterpret_cast<unsigned long long *>(&sm.wv.fin[k >> 6]), 1ull << (k & 63));
+    }
+    __syncthreads();
+    {
+        // arc -> row: running max of the scattered row starts
+        const int32_t per = (tile_edges + BLOCK - 1) / BLOCK;
+        const int32_t lo = (int32_t)threadIdx.x * per < tile_edges ? (int32_t)threadIdx.x * per : tile_edges;
+        const int32_t hi = lo + per < tile_edges ? lo + per : tile_edges;
+        int m = 0;
+        for (int32_t k = lo; k < hi; k++) {
+            const int x = sm.wv.arow[k];
+            m = x > m ? x : m;
+            sm.wv.arow[k] = (uint16_t)m;
+        }
+        const int before = block_exclusive_max(m, sm.tmp);
+        if (before > 0)
+            for (int32_t k = lo; k < hi; k++)
+                if ((int)sm.wv.arow[k] < before) sm.wv.arow[k] = (uint16_t)before;
+    }
+    __syncthreads();
+
+    // a row whose every contribution from this tile is in x
+    auto finish_row = [&](int32_t k, const uint64_t (&x)[W]) {
+        bool nz = false;
+#pragma unroll
+        for (int w = 0; w < W; w++) nz |= x[w] != 0;
+        if (!nz) return;
+        const int32_t v = r0 + k;
+        uint64_t cv[W], acc[W];
+        load_words<W>(cur + (size_t)v * W, cv);
+        bool any = false;
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            acc[w] = x[w] & ~cv[w];
+            any |= acc[w] != 0;
+        }
+        if (!any) return;
+        if (v >= T.loc_lo && v < r1) {
+#pragma unroll
+            for (int w = 0; w < W; w++) cv[w] |= acc[w];
+            store_words<W>(nxt + (size_t)v * W, cv);
+            atomicOr(reinterpret_cast<unsigned long long *>(&sm.wv.stored[k >> 6]), 1ull << (k & 63));
+            pull_claim(sm, T, v);
+        } else if (merge_global<W>(nxt, bits_next, v, acc)) {
+            pull_claim(sm, T, v);
+        }
+    };
+
+    const int32_t wa = (int32_t)(((int64_t)tile_edges * wv) / WAVES);
+    const int32_t wb = (int32_t)(((int64_t)tile_edges * (wv + 1)) / WAVES);
+    int32_t crow = -1;  // row carried from the wave's previous step (wave-uniform)
+    uint64_t cacc[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) cacc[w] = 0;
+    for (int32_t base = wa; base < wb; base += 64) {
+        const int32_t k = base + lane;
+        const bool in = k < wb;
+        const int32_t rk = in ? (int32_t)sm.wv.arow[k] : 0;  // a valid row index on every lane
+        const int32_t ro = in ? rk : 0x7fffffff;              // lanes past the range match no row
+        const bool active = in && !((sm.wv.fin[rk >> 6] >> (rk & 63)) & 1ull);
+        uint64_t x[W];
+#pragma unroll
+        for (int w = 0; w < W; w++) x[w] = 0;
+        if (__ballot(active)) {
+            const int32_t u = active ? gr.col[e0 + k] : r0;
+            const uint64_t hm = active ? ~0ull : 0ull;
+            load_words<W>(cur + (size_t)u * W, x);
+#pragma unroll
+            for (int w = 0; w < W; w++) x[w] &= hm;
+            // segmented OR-scan: lanes of one row are consecutive
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int32_t rup = __shfl_up(ro, d, 64);
+                const bool take = lane >= d && rup == ro;
+#pragma unroll
+                for (int w = 0; w < W; w++) {
+                    const uint64_t y = shfl_up64(x[w], d);
+                    if (take) x[w] |= y;
+                }
+            }
+        }
+        const int32_t rdown = __shfl_down(ro, 1, 64);
+        const bool tail = in && (lane == 63 || rdown != ro || k + 1 == wb);
+        if (tail && ro == crow) {
+#pragma unroll
+            for (int w = 0; w < W; w++) x[w] |= cacc[w];
+        }
+        const int32_t re = in ? (int32_t)sm.rend[rk] : 0;
+        const bool closes = tail && k + 1 == re;            // the row's last arc in the tile
+        const bool leaves = tail && !closes && k + 1 == wb;  // open past this wave's range
+        const bool carries = tail && !closes && !leaves;     // only lane 63
+        if (closes) {
+            if (rstart_off(rk) >= wa) {
+                finish_row(rk, x);
+            } else {
+                sm.wv.pend_row[wv] = rk;
+#pragma unroll
+                for (int w = 0; w < W; w++) sm.wv.pend_acc[wv][w] = x[w];
+            }
+        } else if (leaves) {
+            sm.wv.out_row[wv] = rk;
+#pragma unroll
+            for (int w = 0; w < W; w++) sm.wv.out_acc[wv][w] = x[w];
+        }
+        // carry into the next step, and stop gathering for a completed row
+        if (__shfl((int)carries, 63, 64)) {
+            crow = __shfl(ro, 63, 64);
+#pragma unroll
+            for (int w = 0; w < W; w++) cacc[w] = shfl64(x[w], 63);
+            if (lane == 0) {
+                uint64_t cv[W];
+                load_words<W>(cur + (size_t)(r0 + crow) * W, cv);
+                bool f = true;
+#pragma unroll
+                for (int w = 0; w < W; w++) f &= (cacc[w] | cv[w]) == full[w];
+                if (f) atomicOr(reinterpret_cast<unsigned long long *>(&sm.wv.fin[crow >> 6]), 1ull << (crow & 63));
+            }
+        } else {
+            crow = -1;
+        }
+    }
+    __syncthreads();
+    // rows split between waves: the closing wave's share plus the earlier ones;
+    // the row continuing past the tile merges globally
+    if (threadIdx.x < WAVES) {
+        const int w0 = threadIdx.x;
+        const int32_t rk = sm.wv.pend_row[w0];
+        if (rk >= 0) {
+            uint64_t x[W];
+#pragma unroll
+            for (int w = 0; w < W; w++) x[w] = sm.wv.pend_acc[w0][w];
+            for (int w1 = 0; w1 < w0; w1++)
+                if (sm.wv.out_row[w1] == rk) {
+#pragma unroll
+                    for (int w = 0; w < W; w++) x[w] |= sm.wv.out_acc[w1][w];
+                }
+            finish_row(rk, x);
+        }
+    } else if (threadIdx.x == WAVES) {
+        int32_t rk = -1;
+        for (int w1 = 0; w1 < WAVES; w1++)
+            if (sm.wv.out_row[w1] >= 0 && (int32_t)sm.rend[sm.wv.out_row[w1]] > tile_edges) rk = sm.wv.out_row[w1];
+        if (rk >= 0) {
+            uint64_t x[W];
+#pragma unroll
+            for (int w = 0; w < W; w++) x[w] = 0;
+            for (int w1 = 0; w1 < WAVES; w1++)
+                if (sm.wv.out_row[w1] == rk) {
+#pragma unroll
+                    for (int w = 0; w < W; w++) x[w] |= sm.wv.out_acc[w1][w];
+                }
+            finish_row(rk, x);
+        }
+    }
+    __syncthreads();
+    // vertex phase of the rows whose end item is in this tile
+    for (int32_t v = r0 + (int32_t)threadIdx.x; v < r1; v += BLOCK) {
+        if (!((bits_cur[v >> 6] >> (v & 63)) & 1ull)) continue;
+        const int32_t k = v - r0;
+        if (v < T.loc_lo) {
+            vertex_phase<W, WC, true>(s, g, o, gr.n, round, v);  // tile-crossing row
+        } else {
+            if (!((sm.wv.stored[k >> 6] >> (k & 63)) & 1ull)) {
+                uint64_t cv[W];
+                load_words<W>(cur + (size_t)v * W, cv);
+                store_words<W>(nxt + (size_t)v * W, cv);
+            }
+            vertex_phase<W, WC, false>(s, g, o, gr.n, round, v);
+        }
+    }
+    __syncthreads();
+}
+
+template <int W, int WC>
+__device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
+                          const OutArgs &o, int32_t round, int32_t t, int32_t form)
+{
+    const PullTile T = pull_coords(gr, t);
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k <= T.tile_rows; k += BLOCK) {
+        const int32_t r = T.r0 + k;
+        int32_t x = ((int64_t)r < gr.n ? gr.row_ptr[r + 1] : T.e1) - T.e0;
+        sm.rend[k] = (uint16_t)(x > T.tile_edges + 1 ? T.tile_edges + 1 : x);
+    }
+    for (int32_t k = threadIdx.x; k < T.nclaim; k += BLOCK) sm.claimed[k] = 0;
+    if (threadIdx.x == 0) sm.degsum = 0;
+    if (form == PULL_WAVE) pull_wave<W, WC>(sm, s, gr, g, o, round, T);
+    else pull_walk<W, WC>(sm, s, gr, g, o, round, T);
 
     // frontier flush: one claimed word per thread (nclaim <= BLOCK)
-    auto deg_of = [&](int32_t v) { return (v == r1 ? end_r1 : rend_of(v)) - rstart_of(v); };
+    const int32_t r0 = T.r0, r1 = T.r1, e0 = T.e0;
+    uint64_t *bits_next = bits_buf(s, (round + 1) % 3);
+    auto deg_of = [&](int32_t v) {
+        const int32_t k = v - r0;
+        const int32_t st = k == 0 ? T.start_r0 : e0 + (int32_t)sm.rend[k - 1];
+        return (v == r1 ? T.end_r1 : e0 + (int32_t)sm.rend[k]) - st;
+    };
     uint64_t word = 0;
     int pieces = 0;
-    if ((int32_t)threadIdx.x < nclaim) {
+    if ((int32_t)threadIdx.x < T.nclaim) {
         word = sm.claimed[threadIdx.x];
         if (word) {
-            const int64_t wi = (int64_t)wbase + threadIdx.x;
-            if (wi * 64 >= loc_lo && wi * 64 + 63 < r1) bits_next[wi] = word;
+            const int64_t wi = (int64_t)T.wbase + threadIdx.x;
+            if (wi * 64 >= T.loc_lo && wi * 64 + 63 < r1) bits_next[wi] = word;
             else atomicOr(reinterpret_cast<unsigned long long *>(bits_next + wi), word);
             unsigned long long dsum = 0;
             for (uint64_t x = word; x; x &= x - 1) {
@@ -431,7 +720,7 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     }
     __syncthreads();
     int64_t *dst = q_buf(s, round + 1) + sm.base + off;
-    const int64_t wi = (int64_t)wbase + threadIdx.x;
+    const int64_t wi = (int64_t)T.wbase + threadIdx.x;
     for (uint64_t x = word; x; x &= x - 1) {
         const int32_t v = (int32_t)(wi * 64 + __builtin_ctzll(x));
         const int pc = pieces_of(deg_of(v));

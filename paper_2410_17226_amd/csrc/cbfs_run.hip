@@ -349,11 +349,12 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
             (dense ? rs.pull_rounds : rs.push_rounds)++;
             rs.frontier_vertices += verts;
             rs.frontier_arcs += degsum;
-            // a frontier carrying most of the arcs: every neighbour's set is
-            // OR-ed without the membership test (the sets of non-members add
-            // nothing new, Section 3.2, and the test would pass for most arcs)
-            const int32_t test = !(p.gamma > 0.0f && (double)degsum > (double)p.gamma * (double)p.m);
-            if (dense) e = PROF(CBFS_KERNEL_PULL, st, launch_pull(p.W, p.WC, s, gr, gd, o, round, test, st));
+            // a frontier carrying most of the arcs: the wave form gathers every
+            // neighbour's set (the sets of non-members add nothing new, Section
+            // 3.2, and the membership test would pass for most arcs)
+            const int32_t form = p.gamma > 0.0f && (double)degsum > (double)p.gamma * (double)p.m ? PULL_WAVE
+                                                                                                : PULL_WALK;
+            if (dense) e = PROF(CBFS_KERNEL_PULL, st, launch_pull(p.W, p.WC, s, gr, gd, o, round, form, st));
             else e = PROF(CBFS_KERNEL_PUSH, st, launch_push(p.W, p.WC, s, gr, gd, o, round, pieces, degsum, st));
             if (e != hipSuccess) return hip_fail(dense ? "pull" : "push", e);
         }
