@@ -33,6 +33,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "source-GTEPS (sources×edges/s) + %HBM roofline; batched vs plain; query p50/p99"
 KERNEL_SOURCES = ["cbfs_device.h", "cbfs_round.h", "cbfs_kernels.hip", "cbfs_kernels.h"]
+WORKLOAD_NAMES = {
+    "rmat22": ("rmat22_batch256", "R-MAT scale 22 ef 16 (0.57,0.19,0.19,0.05)"),
+    "grid4096": ("grid4096_batch128", "4096x4096 4-neighbour grid, 5% of edges deleted"),
+    "chunglu25": ("chunglu25_batch64", "Chung-Lu beta 2.1, n 2^25, average degree 30"),
+}
 
 
 def kernel_hash() -> str:
@@ -58,10 +63,10 @@ def algorithmic_bytes(n, m, stats, C, k_w, R):
     return traversal + own_state + outputs + init
 
 
-def load_traffic(kind: str):
+def load_traffic(kind: str, workload: str):
     """Measured HBM bytes per launch from committed rocprofv3 counter runs,
     only if they were taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"{kind}_rmat22_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -83,6 +88,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-clusters", type=int, default=2, help="clusters in the CPU oracle sample")
     ap.add_argument("--no-query", action="store_true")
+    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "grid4096", "chunglu25"],
+                    help="batch workload (the default is the headline one)")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the launch knobs on the first 16 clusters before timing (untimed)")
     ap.add_argument("--copy-only", type=int, default=0,
@@ -108,14 +115,16 @@ def main():
     import synth
     from synth import configs
 
-    cfg = configs.WORKLOADS["rmat22"]
+    cfg = configs.WORKLOADS[args.workload]
     t0 = time.time()
-    a, b, c = cfg["abc"]
-    n_in, src, dst = synth.rmat_edges(cfg["scale"], cfg["edge_factor"], a, b, c, seed=cfg["seed"])
+    n_in, src, dst = configs.raw_graph(args.workload)
     rp, col, _ = P.build_csr(n_in, src, dst)
     del src, dst
     n, m = rp.size - 1, col.size
-    centers = P.top_degree(rp, cfg["count"])
+    if cfg["centers"] == "top_degree":
+        centers = P.top_degree(rp, cfg["count"])
+    else:
+        centers = synth.random_centers(n, cfg["count"], cfg["seed"]).astype(np.int32)
     cptr, sources = P.select_clusters(rp, col, centers, cfg["k"], cfg["hops"])
     R = cfg["R"]
     C = cptr.size - 1
@@ -190,7 +199,7 @@ def main():
         per_launch = B_alg_step * prof_steps / launches
         unit_note = "batch bytes spread over the launches"
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(kind)
+    traffic = load_traffic(kind, args.workload)
     roofline = {"bound": "hbm", "kernel": kind, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": int(per_launch), "avg_launch_ms": round(avg_ms, 3), "launches": launches,
@@ -238,7 +247,7 @@ def main():
     # serving: labels of the first 128 clusters (the top-128 centers) kept on
     # the device; Poisson streams of uniform s-t queries at fixed rates
     query = None
-    if not args.no_query:
+    if not args.no_query and args.workload == "rmat22":
         from paper_2410_17226_amd import server
         CQ = min(128, C)
         dvm, mvm = P.labels_pack(dist[:CQ], masks[:CQ], R)
@@ -271,7 +280,7 @@ def main():
         "metric": METRIC, "value": round(gteps, 2), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "rmat22_batch256", "graph": "R-MAT scale 22 ef 16 (0.57,0.19,0.19,0.05)",
+        "config": {"workload": WORKLOAD_NAMES[args.workload][0], "graph": WORKLOAD_NAMES[args.workload][1],
                    "n": n, "m_arcs": m, "clusters": C, "sources_per_cluster": int(cfg["k"]), "radius": R,
                    "group_words": stats["group_words"], "mode": stats["mode"], "slots": stats["slots"],
                    "parallelism": "single GPU"},

@@ -177,10 +177,9 @@ typedef struct {
     int32_t schedule;          /* persistent mode: 0 = fixed stride over the items
                                   (default), 1 = blocks take work items from a shared
                                   counter                                               */
-    float gamma;               /* a pull round ORs every neighbour's set, without the
-                                  frontier-bitmap test, when sum deg(F) > gamma * m
-                                  (the test would pass for most arcs anyway); 0 = auto
-                                  (0.5), < 0 = always test                              */
+    float gamma;               /* a group's first pull round runs in the wave form (every
+                                  neighbour's set OR-ed, no frontier-bitmap test) when
+                                  sum deg(F) > gamma * m; 0 = auto (0.5), < 0 = never   */
 } cbfs_tuning;
 
 /* Bytes of device workspace cbfs_run_batch needs for these arguments. */

@@ -220,6 +220,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
     __shared__ int64_t s_work[MAX_SLOTS];   // push chunks or pull tiles
     __shared__ int64_t s_nq[MAX_SLOTS];     // pieces in F_i
     __shared__ int32_t s_epb[MAX_SLOTS];    // queue entries per push chunk
+    __shared__ int32_t s_pulls[MAX_SLOTS];  // dense rounds so far
     __shared__ int64_t s_nprev[MAX_SLOTS];  // pieces in F_{i-1}
     __shared__ int64_t s_pref[MAX_SLOTS + 1];
     __shared__ int tmp[WAVES + 1];
@@ -265,6 +266,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
         }
         if (threadIdx.x < MAX_SLOTS) {
             s_dense[threadIdx.x] = a.force_pull ? 1 : 0;
+            s_pulls[threadIdx.x] = 0;
             s_done[threadIdx.x] = 0;
         }
         if ((aborted = grid_barrier(a.ctl, die, ndies, a.err, s_abort))) break;
@@ -287,9 +289,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                     else if (a.alpha < 0.f) dense = 0;
                     else if (!dense) dense = (double)(verts + degsum) > (double)a.gr.m / a.alpha;
                     else dense = (double)verts > (double)a.gr.n / a.beta;
-                    // 2: pull over every neighbour, without the membership test
-                    if (dense && a.gamma > 0.f && (double)degsum > (double)a.gamma * (double)a.gr.m) dense = 2;
-                    else if (dense) dense = 1;
+                    // 2: the wave form over every neighbour (first dense round with
+                    // a frontier carrying most arcs), 1: the walking form
+                    if (dense && s_pulls[sl_me] == 0 && a.gamma > 0.f &&
+                        (double)degsum > (double)a.gamma * (double)a.gr.m)
+                        dense = 2;
+                    else if (dense)
+                        dense = 1;
+                    if (dense) s_pulls[sl_me]++;
                     s_dense[sl_me] = dense;
                     const int32_t epb = push_entries_per_block(pieces, degsum);
                     s_epb[sl_me] = epb;

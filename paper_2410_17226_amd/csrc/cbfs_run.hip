@@ -330,6 +330,7 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
         if ((e = PROF(CBFS_KERNEL_SEED, st, launch_seed(p.W, p.WC, s, gr, gd, d_src, d_cptr, st))) != hipSuccess)
             return hip_fail("seed", e);
         bool dense = false;
+        int32_t pulls = 0;
         for (int32_t round = 0;; round++) {
             if (round > max_rounds) return fail(CBFS_E_HIP, "cbfs_run_batch: level loop did not terminate");
             if ((e = hipMemcpyAsync(hc, s.ctr + 4 * (round & 3), 3 * sizeof(unsigned long long),
@@ -349,11 +350,14 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
             (dense ? rs.pull_rounds : rs.push_rounds)++;
             rs.frontier_vertices += verts;
             rs.frontier_arcs += degsum;
-            // a frontier carrying most of the arcs: the wave form gathers every
-            // neighbour's set (the sets of non-members add nothing new, Section
-            // 3.2, and the membership test would pass for most arcs)
-            const int32_t form = p.gamma > 0.0f && (double)degsum > (double)p.gamma * (double)p.m ? PULL_WAVE
-                                                                                                : PULL_WALK;
+            // the group's first dense round, with a frontier carrying most of
+            // the arcs: few rows can be complete yet, and the wave form gathers
+            // every neighbour's set (the sets of non-members add nothing new,
+            // Section 3.2, and the membership test would pass for most arcs)
+            const int32_t form =
+                pulls == 0 && p.gamma > 0.0f && (double)degsum > (double)p.gamma * (double)p.m ? PULL_WAVE
+                                                                                               : PULL_WALK;
+            if (dense) pulls++;
             if (dense) e = PROF(CBFS_KERNEL_PULL, st, launch_pull(p.W, p.WC, s, gr, gd, o, round, form, st));
             else e = PROF(CBFS_KERNEL_PUSH, st, launch_push(p.W, p.WC, s, gr, gd, o, round, pieces, degsum, st));
             if (e != hipSuccess) return hip_fail(dense ? "pull" : "push", e);
