@@ -350,13 +350,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
             if (s_stop) break;
             // the work counter of round i+2 last served round i-1
             if (blockIdx.x == 0 && threadIdx.x == 0) a.work[(round + 2) % 3] = 0;
-            // blocks take GRAB items at a time from the round's counter (or a
-            // fixed stride), items being slot-major: push chunks or pull tiles,
-            // then bitmap clears
+            // blocks take items at a fixed stride of one (or GRAB at a time from
+            // the round's counter), items being slot-major: push chunks or pull
+            // tiles, then bitmap clears
             const int64_t total = s_pref[active];
             unsigned long long *wctr = a.work + (round % 3);
+            const int64_t grab = a.schedule == 1 ? GRAB : 1;
             int32_t sl = 0;
-            for (int64_t next = (int64_t)blockIdx.x * GRAB;; next += (int64_t)nb * GRAB) {
+            for (int64_t next = (int64_t)blockIdx.x * grab;; next += (int64_t)nb * grab) {
                 if (a.schedule == 1) {
                     if (threadIdx.x == 0) s_grab = (int64_t)atomicAdd(wctr, (unsigned long long)GRAB);
                     __syncthreads();
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                 }
                 const int64_t first = next;
                 if (first >= total) break;
-                const int64_t last = first + GRAB < total ? first + GRAB : total;
+                const int64_t last = first + grab < total ? first + grab : total;
                 for (int64_t item = first; item < last; item++) {
                     if (item < s_pref[sl]) sl = 0;
                     while (item >= s_pref[sl + 1]) sl++;
