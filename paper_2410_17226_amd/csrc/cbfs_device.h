@@ -43,6 +43,11 @@ constexpr int PULL_ROW_WORDS = (TILE_ITEMS + 1 + 63) / 64;  // one bit per row o
 static_assert(PULL_CLAIM_WORDS <= BLOCK, "one claimed word per thread at a pull tile's flush");
 enum { PULL_WALK = 0, PULL_WAVE = 1 };  // forms of the pull round
 constexpr int STAGE_CAP = 1024;     // LDS frontier staging capacity per push/seed block
+// arcs per pass when each push thread walks its own entry (wide groups hold
+// fewer neighbour sets in registers)
+template <int W>
+constexpr int push_direct_batch() { return W <= 2 ? 4 : 2; }
+static_assert(BLOCK * 4 <= STAGE_CAP, "one direct push pass fits the LDS stager");
 constexpr int MAX_W = 8;            // max words per vertex in a group
 constexpr uint32_t UNREACHED = 0xFFFFFFFFu;
 constexpr int32_t E_RADIUS = -5;

@@ -125,7 +125,8 @@ __device__ void seed_block(Stager<STAGE_CAP> &st, const SlotArgs &s, const Graph
 // entries (pieces of <= PIECE arcs; epb from push_entries_per_block, so a
 // chunk holds about PUSH_BLOCK_ARCS arcs): the vertex phase for first pieces, then the
 // chunk's arcs spread evenly over the block (block scan + binary search of
-// each arc's owner).  Per arc (u, v): x = Seen_i(u) \ Seen_i(v); if not empty,
+// each arc's owner), or, when every entry has at most a few arcs, each thread
+// walks its own entry's arcs.  Per arc (u, v): x = Seen_i(u) \ Seen_i(v); if not empty,
 // 64-bit atomic OR into nxt(v) and claim v (the Fetch_And_Or and
 // compare_and_swap of the paper's edge phase).
 // ---------------------------------------------------------------------------
@@ -144,18 +145,53 @@ __device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &
     unsigned long long *ctr_next = ctr_buf(s, round + 1);
 
     int cnt = 0;
+    int32_t lo = 0;
+    uint64_t cu[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) cu[w] = 0;
     const int64_t idx = first + threadIdx.x;
     if ((int32_t)threadIdx.x < epb && idx < nq) {
         const int64_t e = q_buf(s, round)[idx];
         const int32_t u = (int32_t)(e & 0xffffffff);
         const int32_t p = (int32_t)(e >> 32);
         const int32_t rs = gr.row_ptr[u], re = gr.row_ptr[u + 1];
-        const int32_t lo = rs + p * PIECE;
+        lo = rs + p * PIECE;
         const int32_t hi = re < lo + PIECE ? re : lo + PIECE;
         cnt = hi > lo ? hi - lo : 0;
-        uint64_t cu[W];
         load_words<W>(cur + (size_t)u * W, cu);
         if (p == 0) vertex_phase<W, WC>(s, g, o, gr.n, round, u);
+    }
+    // every entry short (a low-degree frontier): each thread pushes its own
+    // arcs, DB at a time, with no block scan or owner search
+    constexpr int DB = push_direct_batch<W>();
+    if (__syncthreads_and(cnt <= 2 * DB)) {
+        const int iters = __syncthreads_or(cnt > DB) ? 2 : 1;
+        for (int it = 0; it < iters; it++) {
+            const int32_t j0 = it * DB;
+            int32_t v[DB];
+#pragma unroll
+            for (int j = 0; j < DB; j++) v[j] = j0 + j < cnt ? gr.col[lo + j0 + j] : -1;
+            uint64_t cv[DB][W];
+#pragma unroll
+            for (int j = 0; j < DB; j++) load_words<W>(cur + (size_t)(v[j] >= 0 ? v[j] : 0) * W, cv[j]);
+#pragma unroll
+            for (int j = 0; j < DB; j++) {
+                if (v[j] < 0) continue;
+                uint64_t x[W];
+                bool any = false;
+#pragma unroll
+                for (int w = 0; w < W; w++) {
+                    x[w] = cu[w] & ~cv[j][w];
+                    any |= x[w] != 0;
+                }
+                if (any) contribute<W>(sm.st, nxt, bits_next, gr.row_ptr, v[j], x);
+            }
+            // at most BLOCK * DB <= STAGE_CAP claims per pass
+            stager_flush(sm.st, gr.row_ptr, q_next, ctr_next);
+        }
+        return;
+    }
+    if ((int32_t)threadIdx.x < epb && idx < nq) {
         sm.estart[threadIdx.x] = lo;
 #pragma unroll
         for (int w = 0; w < W; w++) sm.cu[threadIdx.x * W + w] = cu[w];
