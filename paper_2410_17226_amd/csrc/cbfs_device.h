@@ -248,37 +248,44 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
 }
 
 // Vertex phase for u in F_i (lines computing S_new, Delta_u, the subset write
-// and the seen update), one cluster of the group at a time: new = Seen_i(u) \
+// and the seen update) for cluster j of the group: new = Seen_i(u) \
 // Seen_{i-1}(u) from cur and seen.  With NXT_OR, nxt(u) receives the new bits
 // by atomic OR so that nxt(u) covers Seen_i(u) by the end of the round;
 // without it the caller stores nxt(u) itself (it owns u's row in this round).
+template <int W, int WC, bool NXT_OR>
+__device__ __forceinline__ void vertex_phase_cluster(const SlotArgs &s, const GroupDesc &g, const OutArgs &o,
+                                                     int64_t n, int32_t round, int32_t u, int32_t j)
+{
+    const uint64_t *cp = cur_buf(s, round) + (size_t)u * W + j * WC;
+    uint64_t *sp = s.seen + (size_t)u * W + j * WC;
+    uint64_t cu[WC], sv[WC], nw[WC];
+    uint64_t any = 0;
+#pragma unroll
+    for (int x = 0; x < WC; x++) {
+        cu[x] = cp[x];
+        sv[x] = sp[x];
+        nw[x] = cu[x] & ~sv[x];
+        any |= nw[x];
+    }
+    if (!any) return;
+#pragma unroll
+    for (int x = 0; x < WC; x++) {
+        sp[x] = cu[x];
+        if constexpr (NXT_OR)
+            if (nw[x]) or64(nxt_buf(s, round) + (size_t)u * W + j * WC + x, nw[x]);
+    }
+    emit_cluster<WC>(o, n, g.c0 + j, u, round, sv, nw, g.full + j * WC);
+}
+
+// The vertex phase of u for every cluster of the group, one after another.
 template <int W, int WC, bool NXT_OR = true>
 __device__ __forceinline__ void vertex_phase(const SlotArgs &s, const GroupDesc &g, const OutArgs &o,
                                              int64_t n, int32_t round, int32_t u)
 {
-    const uint64_t *cp = cur_buf(s, round) + (size_t)u * W;
-    uint64_t *sp = s.seen + (size_t)u * W;
-    uint64_t *np = nxt_buf(s, round) + (size_t)u * W;
 #pragma unroll 1
     for (int j = 0; j < W / WC; j++) {
         if (j >= g.nc) break;
-        uint64_t cu[WC], sv[WC], nw[WC];
-        uint64_t any = 0;
-#pragma unroll
-        for (int x = 0; x < WC; x++) {
-            cu[x] = cp[j * WC + x];
-            sv[x] = sp[j * WC + x];
-            nw[x] = cu[x] & ~sv[x];
-            any |= nw[x];
-        }
-        if (!any) continue;
-#pragma unroll
-        for (int x = 0; x < WC; x++) {
-            sp[j * WC + x] = cu[x];
-            if constexpr (NXT_OR)
-                if (nw[x]) or64(np + j * WC + x, nw[x]);
-        }
-        emit_cluster<WC>(o, n, g.c0 + j, u, round, sv, nw, g.full + j * WC);
+        vertex_phase_cluster<W, WC, NXT_OR>(s, g, o, n, round, u, j);
     }
 }
 

@@ -478,11 +478,14 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         for (int w = 0; w < W; w++) acc[w] = slot[w];
         finish_local(pend, cv, acc);
     }
-    // vertex phase of the rows whose end item is in this tile
-    for (int32_t v = r0 + (int32_t)threadIdx.x; v < r1; v += BLOCK) {
-        if (!((bits_cur[v >> 6] >> (v & 63)) & 1ull)) continue;
-        if (v < T.loc_lo) vertex_phase<W, WC, true>(s, g, o, gr.n, round, v);  // tile-crossing row
-        else vertex_phase<W, WC, false>(s, g, o, gr.n, round, v);
+    // vertex phase of the rows whose end item is in this tile, one thread per
+    // (row, cluster): the threads of a row read its words together
+    constexpr int CPV = W / WC;
+    for (int32_t idx = threadIdx.x; idx < (r1 - r0) * CPV; idx += BLOCK) {
+        const int32_t v = r0 + idx / CPV, j = idx % CPV;
+        if (j >= g.nc || !((bits_cur[v >> 6] >> (v & 63)) & 1ull)) continue;
+        if (v < T.loc_lo) vertex_phase_cluster<W, WC, true>(s, g, o, gr.n, round, v, j);  // tile-crossing row
+        else vertex_phase_cluster<W, WC, false>(s, g, o, gr.n, round, v, j);
     }
     __syncthreads();
 }
@@ -683,19 +686,22 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         }
     }
     __syncthreads();
-    // vertex phase of the rows whose end item is in this tile
-    for (int32_t v = r0 + (int32_t)threadIdx.x; v < r1; v += BLOCK) {
-        if (!((bits_cur[v >> 6] >> (v & 63)) & 1ull)) continue;
+    // vertex phase of the rows whose end item is in this tile, one thread per
+    // (row, cluster); a local row the arc phase did not store gets nxt(v) =
+    // Seen_i(v) here, each thread its cluster's words
+    constexpr int CPV = W / WC;
+    for (int32_t idx = threadIdx.x; idx < (r1 - r0) * CPV; idx += BLOCK) {
+        const int32_t v = r0 + idx / CPV, j = idx % CPV;
+        if (j >= g.nc || !((bits_cur[v >> 6] >> (v & 63)) & 1ull)) continue;
         const int32_t k = v - r0;
         if (v < T.loc_lo) {
-            vertex_phase<W, WC, true>(s, g, o, gr.n, round, v);  // tile-crossing row
+            vertex_phase_cluster<W, WC, true>(s, g, o, gr.n, round, v, j);  // tile-crossing row
         } else {
             if (!((sm.wv.stored[k >> 6] >> (k & 63)) & 1ull)) {
-                uint64_t cv[W];
-                load_words<W>(cur + (size_t)v * W, cv);
-                store_words<W>(nxt + (size_t)v * W, cv);
+#pragma unroll
+                for (int x = 0; x < WC; x++) nxt[(size_t)v * W + j * WC + x] = cur[(size_t)v * W + j * WC + x];
             }
-            vertex_phase<W, WC, false>(s, g, o, gr.n, round, v);
+            vertex_phase_cluster<W, WC, false>(s, g, o, gr.n, round, v, j);
         }
     }
     __syncthreads();
