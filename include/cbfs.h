@@ -165,7 +165,7 @@ enum {
 typedef struct {
     int32_t mode;              /* CBFS_MODE_*                                          */
     int32_t group_words;       /* words per vertex of a cluster group: 0 = auto, else a
-                                  multiple of W in {1,2,4,8}                           */
+                                  multiple of W in {1,2,4,8,16}                        */
     int32_t concurrent_groups; /* group slots searched side by side: 0 = auto          */
     int32_t block_size;        /* 0 = auto, else 256                                    */
     float alpha;               /* pull when |F| + sum deg(F) > m / alpha; 0 = auto;

@@ -48,7 +48,7 @@ constexpr int STAGE_CAP = 1024;     // LDS frontier staging capacity per push/se
 template <int W>
 constexpr int push_direct_batch() { return W <= 2 ? 4 : 2; }
 static_assert(BLOCK * 4 <= STAGE_CAP, "one direct push pass fits the LDS stager");
-constexpr int MAX_W = 8;            // max words per vertex in a group
+constexpr int MAX_W = 16;           // max words per vertex in a group
 constexpr uint32_t UNREACHED = 0xFFFFFFFFu;
 constexpr int32_t E_RADIUS = -5;
 

@@ -409,6 +409,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
         else if ((W_) == 8 && (WC_) == 1) { constexpr int W = 8, WC = 1; CALL; } \
         else if ((W_) == 8 && (WC_) == 2) { constexpr int W = 8, WC = 2; CALL; } \
         else if ((W_) == 8 && (WC_) == 4) { constexpr int W = 8, WC = 4; CALL; } \
+        else if ((W_) == 16 && (WC_) == 1) { constexpr int W = 16, WC = 1; CALL; } \
+        else if ((W_) == 16 && (WC_) == 2) { constexpr int W = 16, WC = 2; CALL; } \
+        else if ((W_) == 16 && (WC_) == 4) { constexpr int W = 16, WC = 4; CALL; } \
         else return hipErrorInvalidValue;                                \
     } while (0)
 

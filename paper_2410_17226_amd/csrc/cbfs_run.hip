@@ -119,7 +119,7 @@ struct Plan {
 static bool valid_w(int W, int WC)
 {
     return (W == 1 && WC == 1) || (W == 3 && WC == 3) || (W == 2 && (WC == 1 || WC == 2)) ||
-           (W == 4 && (WC == 1 || WC == 2 || WC == 4)) || (W == 8 && (WC == 1 || WC == 2 || WC == 4));
+           ((W == 4 || W == 8 || W == 16) && (WC == 1 || WC == 2 || WC == 4));
 }
 
 static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *t, Plan &p,
@@ -184,7 +184,7 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
         p.schedule = t->schedule;
     }
     if (!valid_w(p.W, p.WC))
-        return fail(CBFS_E_ARG, "cbfs_tuning: group_words must be one of 1,2,4,8 and a multiple of the cluster words");
+        return fail(CBFS_E_ARG, "cbfs_tuning: group_words must be one of 1,2,4,8,16 and a multiple of the cluster words");
     // never pack more words than clusters need
     p.per_group = p.W / p.WC;
     while (p.per_group > 1 && p.per_group / 2 >= p.C && valid_w(p.W / 2, p.WC)) {
@@ -616,7 +616,7 @@ cbfs_batch sample_of(const cbfs_batch *b, int32_t sample_clusters)
     return s;
 }
 
-const int32_t kTuneWords[] = {1, 2, 4, 8};
+const int32_t kTuneWords[] = {1, 2, 4, 8, 16};
 const int32_t kTuneSlots[] = {4, 8, 16, 32, 64};
 
 }  // namespace
