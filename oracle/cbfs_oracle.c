@@ -456,6 +456,171 @@ int64_t oracle_certificate(int64_t n, const int32_t *row_ptr, const int32_t *col
     return bad;
 }
 
+/* The same certificate evaluated a word of sources at a time, for clusters
+ * too large to decode per source.  For a reached vertex v, level t holds
+ * L_v(t) = {i : delta_i(v) = t}: the plane t - dist[v] + R (empty outside
+ * [0, 2R]).  Per 64-bit word the conditions are:
+ *   the planes of v are pairwise disjoint and together hold every source of
+ *   the cluster (reached v), or are all empty (unreached v);
+ *   the center (bit 0) sits at offset 0, so dist[v] = delta_0(v);
+ *   no level below 0, and L_v(0) = the sources equal to v;
+ *   every arc (v, u): u is reached iff v is, and L_v(t) lies within
+ *   L_u(t-1) | L_u(t) | L_u(t+1) (|delta_i(u) - delta_i(v)| <= 1);
+ *   every t > 0: L_v(t) lies within the union over neighbours u of L_u(t-1)
+ *   (each source has a neighbour one level closer).
+ * Returns the number of (vertex, condition, word) violations. */
+typedef struct {
+    int64_t n;
+    const int32_t *row_ptr, *col;
+    int32_t k;
+    const int32_t *src_v, *src_i;  /* the sources sorted by vertex, and their indices */
+    int32_t R, W;
+    int64_t P;
+    const uint32_t *dist;
+    const uint64_t *masks;
+    uint64_t *scratch;             /* per thread: P * W parent words + W source words */
+    int64_t *bad;
+} certw_ctx;
+
+static uint64_t certw_level(const certw_ctx *c, int64_t v, int64_t t, int32_t w)
+{
+    const uint32_t dv = c->dist[v];
+    if (dv == UINT32_MAX) return 0;
+    const int64_t p = t - (int64_t)dv + c->R;
+    if (p < 0 || p >= c->P) return 0;
+    return c->masks[((size_t)p * c->n + (size_t)v) * c->W + (size_t)w];
+}
+
+static void certw_body(int64_t lo, int64_t hi, int tid, void *p)
+{
+    certw_ctx *c = (certw_ctx *)p;
+    const int64_t n = c->n, P = c->P;
+    const int32_t W = c->W, R = c->R;
+    uint64_t *par = c->scratch + (size_t)tid * (size_t)(P + 1) * W;
+    uint64_t *srcw = par + (size_t)P * W;
+    int64_t bad = 0;
+    for (int64_t v = lo; v < hi; v++) {
+        const uint32_t dv = c->dist[v];
+        /* sources equal to v */
+        for (int32_t w = 0; w < W; w++) srcw[w] = 0;
+        {
+            int32_t a = 0, b = c->k;
+            while (a < b) {
+                const int32_t m = (a + b) / 2;
+                if (c->src_v[m] < v) a = m + 1;
+                else b = m;
+            }
+            for (int32_t j = a; j < c->k && c->src_v[j] == v; j++)
+                srcw[c->src_i[j] / 64] |= 1ull << (c->src_i[j] % 64);
+        }
+        if (dv == UINT32_MAX) {
+            for (int64_t pl = 0; pl < P; pl++)
+                for (int32_t w = 0; w < W; w++)
+                    if (c->masks[((size_t)pl * n + (size_t)v) * W + (size_t)w]) bad++;
+            for (int32_t w = 0; w < W; w++)
+                if (srcw[w]) bad++;
+            for (int32_t e = c->row_ptr[v]; e < c->row_ptr[v + 1]; e++)
+                if (c->dist[c->col[e]] != UINT32_MAX) bad++;
+            continue;
+        }
+        for (int32_t w = 0; w < W; w++) {
+            uint64_t acc = 0;
+            for (int64_t pl = 0; pl < P; pl++) {
+                const uint64_t x = c->masks[((size_t)pl * n + (size_t)v) * W + (size_t)w];
+                if (acc & x) bad++;
+                acc |= x;
+                if ((int64_t)dv + pl - R < 0 && x) bad++;
+            }
+            const int32_t lo_i = 64 * w;
+            uint64_t fullw = 0;
+            if (c->k >= lo_i + 64) fullw = ~0ull;
+            else if (c->k > lo_i) fullw = (1ull << (c->k - lo_i)) - 1;
+            if (acc != fullw) bad++;
+            if (certw_level(c, v, 0, w) != srcw[w]) bad++;
+        }
+        if (!(c->masks[((size_t)R * n + (size_t)v) * W] & 1ull)) bad++;
+        for (int64_t i = 0; i < P * W; i++) par[i] = 0;
+        for (int32_t e = c->row_ptr[v]; e < c->row_ptr[v + 1]; e++) {
+            const int64_t u = c->col[e];
+            const uint32_t du = c->dist[u];
+            if (du == UINT32_MAX) {
+                bad++;
+                continue;
+            }
+            /* level t of v is plane t - du + R of u: shift = dv - du */
+            const int64_t shift = (int64_t)dv - (int64_t)du;
+            for (int64_t pl = 0; pl < P; pl++) {
+                for (int32_t w = 0; w < W; w++) {
+                    const uint64_t x = c->masks[((size_t)pl * n + (size_t)v) * W + (size_t)w];
+                    uint64_t lu[3];  /* u at levels t - 1, t, t + 1 */
+                    for (int q = 0; q < 3; q++) {
+                        const int64_t pu = pl + shift + q - 1;
+                        lu[q] = (pu >= 0 && pu < P) ? c->masks[((size_t)pu * n + (size_t)u) * W + (size_t)w] : 0;
+                    }
+                    if (x & ~(lu[0] | lu[1] | lu[2])) bad++;
+                    par[pl * W + w] |= lu[0];
+                }
+            }
+        }
+        for (int64_t pl = 0; pl < P; pl++) {
+            if ((int64_t)dv + pl - R <= 0) continue;
+            for (int32_t w = 0; w < W; w++)
+                if (c->masks[((size_t)pl * n + (size_t)v) * W + (size_t)w] & ~par[pl * W + w]) bad++;
+        }
+    }
+    c->bad[tid] += bad;
+}
+
+typedef struct {
+    int32_t v, i;
+} src_pair;
+
+static int cmp_src_pair(const void *a, const void *b)
+{
+    const src_pair *x = (const src_pair *)a, *y = (const src_pair *)b;
+    if (x->v != y->v) return (x->v > y->v) - (x->v < y->v);
+    return (x->i > y->i) - (x->i < y->i);
+}
+
+int64_t oracle_certificate_words(int64_t n, const int32_t *row_ptr, const int32_t *col, int32_t k,
+                                 const int32_t *S, int32_t R, int32_t W, const uint32_t *dist,
+                                 const uint64_t *masks, int32_t nthreads)
+{
+    if (n <= 0 || k < 1 || k > 64 * W || R < 0) return OR_E_ARG;
+    int nt = nthreads_or_default(nthreads);
+    const int64_t P = 2 * (int64_t)R + 1;
+    src_pair *sp = (src_pair *)malloc(sizeof(src_pair) * (size_t)k);
+    int32_t *sv = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+    int32_t *si = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+    uint64_t *scratch = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)MAX_THREADS * (size_t)(P + 1) * (size_t)W);
+    if (!sp || !sv || !si || !scratch) {
+        free(sp);
+        free(sv);
+        free(si);
+        free(scratch);
+        return OR_E_NOMEM;
+    }
+    for (int32_t i = 0; i < k; i++) {
+        sp[i].v = S[i];
+        sp[i].i = i;
+    }
+    qsort(sp, (size_t)k, sizeof(src_pair), cmp_src_pair);
+    for (int32_t i = 0; i < k; i++) {
+        sv[i] = sp[i].v;
+        si[i] = sp[i].i;
+    }
+    int64_t bad_by_thread[MAX_THREADS] = {0};
+    certw_ctx cc = {n, row_ptr, col, k, sv, si, R, W, P, dist, masks, scratch, bad_by_thread};
+    parallel_for(n, 1024, nt, certw_body, &cc);
+    int64_t bad = 0;
+    for (int t = 0; t < nt; t++) bad += bad_by_thread[t];
+    free(sp);
+    free(sv);
+    free(si);
+    free(scratch);
+    return bad;
+}
+
 /* ---------------------------------------------------------------------------
  * Graph cleanup.  flags: 1 symmetrize, 2 dedup, 4 drop self-loops, 8 keep the
  * largest connected component (ties: the component holding the smallest

@@ -83,7 +83,7 @@ def _check_sampled(rp, col, cp, src, R, dist, masks, st, exact, certified):
     for c in certified:
         gd = dist[c].cpu().numpy().view(np.uint32)
         gm = masks[c].cpu().numpy().view(np.uint64)
-        bad = oracle.certificate(rp, col, src[cp[c]:cp[c + 1]], R, gd, gm, nthreads=THREADS)
+        bad = oracle.certificate_words(rp, col, src[cp[c]:cp[c + 1]], R, gd, gm, nthreads=THREADS)
         assert bad == 0, f"cluster {c}: {bad} certificate violations"
     _log(f"certificate holds on clusters {list(certified)}")
 

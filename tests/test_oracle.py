@@ -343,17 +343,46 @@ def test_certificate_accepts_oracle_and_rejects_planted_mistakes():
     c = int(oracle.top_degree(rp, 1)[0])
     cl = oracle.cluster_around(rp, col, c, 64, 1)
     dist, masks, st = oracle.cbfs(rp, col, [0, cl.size], cl, R=1)
-    assert oracle.certificate(rp, col, cl, 1, dist[0], masks[0]) == 0
-    bad = masks[0].copy()
-    v = 100
-    w = bad[:, v, 0].copy()            # move source 5's bit to a neighbouring plane
-    p = [i for i in range(3) if (w[i] >> np.uint64(5)) & np.uint64(1)][0]
-    bad[p, v, 0] ^= np.uint64(1 << 5)
-    bad[(p + 1) % 3, v, 0] ^= np.uint64(1 << 5)
-    assert oracle.certificate(rp, col, cl, 1, dist[0], bad) > 0
-    bd = dist[0].copy()
-    bd[200] += 1
-    assert oracle.certificate(rp, col, cl, 1, bd, masks[0]) > 0
+    for cert in (oracle.certificate, oracle.certificate_words):
+        assert cert(rp, col, cl, 1, dist[0], masks[0]) == 0
+        bad = masks[0].copy()
+        v = 100
+        w = bad[:, v, 0].copy()            # move source 5's bit to a neighbouring plane
+        p = [i for i in range(3) if (w[i] >> np.uint64(5)) & np.uint64(1)][0]
+        bad[p, v, 0] ^= np.uint64(1 << 5)
+        bad[(p + 1) % 3, v, 0] ^= np.uint64(1 << 5)
+        assert cert(rp, col, cl, 1, dist[0], bad) > 0
+        bd = dist[0].copy()
+        bd[200] += 1
+        assert cert(rp, col, cl, 1, bd, masks[0]) > 0
+        dropped = masks[0].copy()              # a source missing at one vertex
+        dropped[:, 300, 0] &= ~np.uint64(1 << 7)
+        assert cert(rp, col, cl, 1, dist[0], dropped) > 0
+
+
+def test_certificate_words_agrees_on_wide_disconnected_and_radius2():
+    """Multi-word clusters, unreachable vertices and radius 2: the word form
+    accepts the oracle's exact outputs and rejects a shifted center."""
+    n, s, d = synth.random_graph(300, 0.01, 21)
+    rp, col, _ = oracle.clean_csr(n, s, d, flags=7)   # no LCC: unreachable vertices
+    deg = np.diff(rp)
+    c = int(np.argmax(deg))
+    for R, k in ((1, 150), (2, 64)):
+        cl = oracle.cluster_around(rp, col, c, k, R)
+        dist, masks, st = oracle.cbfs(rp, col, [0, cl.size], cl, R=R)
+        assert st[0] == 0 and (dist[0] == U32MAX).any()
+        assert oracle.certificate(rp, col, cl, R, dist[0], masks[0]) == 0
+        assert oracle.certificate_words(rp, col, cl, R, dist[0], masks[0]) == 0
+    # the center's bit moved off offset 0, with dist moved to keep delta_0(v):
+    # the word form also checks that the center sits at offset 0
+    cl = oracle.cluster_around(rp, col, c, 64, 1)
+    dist, masks, st = oracle.cbfs(rp, col, [0, cl.size], cl, R=1)
+    v = int(np.nonzero((dist[0] != U32MAX) & (dist[0] > 0))[0][0])
+    bd, bm = dist[0].copy(), masks[0].copy()
+    bm[1, v, 0] &= ~np.uint64(1)
+    bm[0, v, 0] |= np.uint64(1)
+    bd[v] += 1
+    assert oracle.certificate_words(rp, col, cl, 1, bd, bm) > 0
 
 
 def test_cleanup_c_matches_numpy_and_scipy():
