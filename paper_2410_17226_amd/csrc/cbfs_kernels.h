@@ -29,7 +29,7 @@ struct PersistArgs {
     const int32_t *sources;     // batch sources
     const int32_t *cluster_ptr; // batch cluster_ptr
     unsigned int *ctl;          // [CTL_WORDS] barrier state, work counters (zeroed before launch)
-    unsigned long long *work;   // [3] per-round work counters
+    unsigned long long *work;   // [3 * DIES] per-round work counters of each die
     int32_t *err;               // 0 ok, 1 barrier timeout, 2 round limit
     long long *stats;           // [num_groups][5]: rounds, push, pull, sum |F|, sum deg(F)
     float alpha, beta, gamma;

@@ -82,24 +82,19 @@ __global__ void k_finalize(SlotArgs s, int64_t n, GroupDesc g, OutArgs o)
 // Persistent batch kernel.
 // ---------------------------------------------------------------------------
 
-// Grid barrier for a cooperative launch, where every block is resident.
+// Barriers of the cooperative launch, where every block is resident.
 //
-// Memory ordering across the dies: each die has its own L2, so an agent-scope
-// release writes the die's dirty L2 lines back and an agent-scope acquire
-// invalidates the die's L2.  The barrier has two levels so that this happens
-// once per die, not once per block:
-//   - every block waits for its own stores to reach L2, then counts itself in
-//     on its die;
-//   - the last block of a die (the die leader) writes the die's L2 back and
-//     counts the die in globally; the last die bumps the generation;
-//   - each die leader, seeing the new generation, invalidates its die's L2 and
-//     then opens its die; the other blocks of the die, seeing the die open,
-//     take their own acquire (their compute unit's L1).
-// Arrivals and polls are relaxed atomics, performed coherently without
-// touching cached data.  The waits are bounded: after BARRIER_TIMEOUT_TICKS of
-// the constant-rate wall clock (or once another block has aborted) a block
-// raises the abort flag, and every block leaves its loops at the next check,
-// so the grid always drains.
+// One flat barrier over all blocks registers each block on its die (XCD, read
+// from HW_REG_XCC_ID).  After that the work is partitioned by die, and each
+// level of the search ends in a barrier over the blocks of one die only: every
+// block waits for its own stores to reach L2 and counts itself in; the last
+// arrival releases at agent scope (the die's dirty L2 lines go out) and opens
+// the die's next generation; every block then acquires at agent scope before
+// reading the level's results.  Arrivals and polls are relaxed atomics,
+// performed coherently without touching cached data.  The waits are bounded:
+// after BARRIER_TIMEOUT_TICKS of the constant-rate wall clock (or once another
+// block has aborted) a block raises the abort flag, and every block leaves its
+// loops at the next check, so the grid always drains.
 constexpr unsigned long long BARRIER_TIMEOUT_TICKS = 400000000ull;  // 4 s at 100 MHz
 
 __device__ __forceinline__ unsigned int ld_relaxed(const unsigned int *p)
@@ -152,36 +147,26 @@ __device__ bool flat_barrier(unsigned int *ctl, unsigned int nblocks, int32_t *a
     return s_abort != 0;
 }
 
-__device__ __forceinline__ bool grid_barrier(unsigned int *ctl, unsigned int die, unsigned int ndies,
-                                             int32_t *abort_flag, int32_t &s_abort)
+// Barrier over the blocks of one die: the last arrival releases (agent scope)
+// and opens the die's next generation; every block then acquires (agent
+// scope).  Blocks of other dies are not involved.
+__device__ __forceinline__ bool die_barrier(unsigned int *ctl, unsigned int die, unsigned int dtotal,
+                                            int32_t *abort_flag, int32_t &s_abort)
 {
     __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned int *gen = ctl + CTL_LINE * CTL_GEN, *count = ctl + CTL_LINE * CTL_COUNT;
         unsigned int *dcount = ctl + CTL_LINE * (CTL_DIE_COUNT + die);
         unsigned int *dgen = ctl + CTL_LINE * (CTL_DIE_GEN + die);
-        const unsigned int dtotal = ld_relaxed(ctl + CTL_LINE * (CTL_DIE_TOTAL + die));
         const unsigned int dg = ld_relaxed(dgen);
-        const unsigned int g = ld_relaxed(gen);
         if (__hip_atomic_fetch_add(dcount, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == dtotal - 1) {
-            // die leader: every block of the die has arrived
             __hip_atomic_store(dcount, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ndies - 1) {
-                __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                wait_change(gen, g, abort_flag);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the die's L2 and this L1
-            __builtin_amdgcn_s_waitcnt(0);
             __hip_atomic_fetch_add(dgen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             wait_change(dgen, dg, abort_flag);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         // one read of the flag for the whole block, so every wave takes the same exit
         s_abort = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     }
@@ -194,22 +179,28 @@ __device__ __forceinline__ unsigned long long ld_ctr(const unsigned long long *p
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Block-uniform: copy slot `sl`'s descriptors into LDS, where the global
-// stores of the round cannot alias them, and record which slot they hold.
-// Every write of these LDS words happens here, between two barriers, so every
-// wave reads the same values afterwards.
-__device__ __forceinline__ void load_desc(const PersistArgs &a, int32_t wave0, int32_t sl, SlotArgs &s_slot,
-                                          GroupDesc &s_group, int32_t &s_cached)
+// Block-uniform: copy the descriptors of slot `slot` (holding group `group`)
+// into LDS, where the global stores of the round cannot alias them, and
+// record which local slot they hold.  Every write of these LDS words happens
+// here, between two barriers, so every wave reads the same values afterwards.
+__device__ __forceinline__ void load_desc(const PersistArgs &a, int32_t slot, int32_t group, int32_t tag,
+                                          SlotArgs &s_slot, GroupDesc &s_group, int32_t &s_cached)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
-        s_slot = a.slots[sl];
-        s_group = a.groups[wave0 + sl];
-        s_cached = sl;
+        s_slot = a.slots[slot];
+        s_group = a.groups[group];
+        s_cached = tag;
     }
     __syncthreads();
 }
 
+// The batch, partitioned by die: after one device-wide registration, the
+// groups are dealt to the dies that have blocks (group g to die rank g mod
+// nd) and so are the slots (die rank r owns slots [r*spd, (r+1)*spd)).  Each
+// die runs its own level loop over its slots with its own barrier, so no
+// data moves between dies during the search, a die's L2 holds only its own
+// groups' frontiers, and a die never waits for another.
 template <int W, int WC>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_persistent(PersistArgs a)
 {
@@ -230,38 +221,49 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
     __shared__ GroupDesc s_group;
     __shared__ int32_t s_cached;
     __shared__ int32_t s_abort;
+    __shared__ uint32_t s_dix, s_ndies, s_drank, s_dtotal;
 
-    __shared__ uint32_t s_ndies;
-
-    const unsigned int nb = gridDim.x;
-    const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t gstride = (int64_t)nb * BLOCK;
-    const int32_t S = a.num_slots;
     const unsigned int die = die_id();
-
-    // register this block on its die, then learn how many dies have blocks
+    // register this block on its die (its index there), then learn the dies
     if (threadIdx.x == 0)
-        __hip_atomic_fetch_add(a.ctl + CTL_LINE * (CTL_DIE_TOTAL + die), 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    bool aborted = flat_barrier(a.ctl, nb, a.err, s_abort);
+        s_dix = __hip_atomic_fetch_add(a.ctl + CTL_LINE * (CTL_DIE_TOTAL + die), 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+    bool aborted = flat_barrier(a.ctl, gridDim.x, a.err, s_abort);
     if (threadIdx.x == 0) {
-        uint32_t k = 0;
-        for (int d = 0; d < DIES; d++) k += ld_relaxed(a.ctl + CTL_LINE * (CTL_DIE_TOTAL + d)) > 0 ? 1 : 0;
+        uint32_t k = 0, r = 0;
+        for (int d = 0; d < DIES; d++)
+            if (ld_relaxed(a.ctl + CTL_LINE * (CTL_DIE_TOTAL + d)) > 0) {
+                if ((unsigned int)d < die) r++;
+                k++;
+            }
         s_ndies = k;
+        s_drank = r;
+        s_dtotal = ld_relaxed(a.ctl + CTL_LINE * (CTL_DIE_TOTAL + die));
     }
     __syncthreads();
-    const unsigned int ndies = s_ndies;
+    const int32_t S = a.num_slots;
+    const int32_t nd = (int32_t)s_ndies < S ? (int32_t)s_ndies : S;  // dies that take groups
+    const int32_t drank = (int32_t)s_drank;
+    const unsigned int dtotal = s_dtotal, dix = s_dix;
+    if (aborted || drank >= nd) return;  // block-uniform; no later barrier counts this die
+    const int32_t spd = S / nd;           // slots of this die
+    const int32_t slot0 = drank * spd;
+    const int32_t Gd = a.num_groups > drank ? (a.num_groups - drank + nd - 1) / nd : 0;
+    const int64_t dtid = (int64_t)dix * BLOCK + threadIdx.x;
+    const int64_t dstride = (int64_t)dtotal * BLOCK;
+    unsigned long long *work = a.work + 3 * die;
 
-    for (int32_t wave0 = 0; wave0 < a.num_groups && !aborted; wave0 += S) {
-        const int32_t active = a.num_groups - wave0 < S ? a.num_groups - wave0 : S;
+    for (int32_t q0 = 0; q0 < Gd && !aborted; q0 += spd) {
+        const int32_t active = Gd - q0 < spd ? Gd - q0 : spd;
+        auto group_of = [&](int32_t sl) { return drank + nd * (q0 + sl); };
         for (int32_t sl = 0; sl < active; sl++) {
-            load_desc(a, wave0, sl, s_slot, s_group, s_cached);
-            init_part<W>(s_slot, a.gr.n, s_group, a.o, gtid, gstride);
+            load_desc(a, slot0 + sl, group_of(sl), sl, s_slot, s_group, s_cached);
+            init_part<W>(s_slot, a.gr.n, s_group, a.o, dtid, dstride);
         }
-        if (gtid < 3) a.work[gtid] = 0;
-        if ((aborted = grid_barrier(a.ctl, die, ndies, a.err, s_abort))) break;
-        for (int32_t sl = blockIdx.x; sl < active; sl += nb) {
-            load_desc(a, wave0, sl, s_slot, s_group, s_cached);
+        if (dix == 0 && threadIdx.x < 3) work[threadIdx.x] = 0;
+        if ((aborted = die_barrier(a.ctl, die, dtotal, a.err, s_abort))) break;
+        for (int32_t sl = (int32_t)dix; sl < active; sl += (int32_t)dtotal) {
+            load_desc(a, slot0 + sl, group_of(sl), sl, s_slot, s_group, s_cached);
             seed_block<W, WC>(sm.push.st, s_slot, a.gr, s_group, a.sources, a.cluster_ptr);
         }
         if (threadIdx.x < MAX_SLOTS) {
@@ -269,15 +271,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
             s_pulls[threadIdx.x] = 0;
             s_done[threadIdx.x] = 0;
         }
-        if ((aborted = grid_barrier(a.ctl, die, ndies, a.err, s_abort))) break;
+        if ((aborted = die_barrier(a.ctl, die, dtotal, a.err, s_abort))) break;
 
         for (int32_t round = 0;; round++) {
             // Decision: thread sl reads slot sl's counters (F_i and F_{i-1});
-            // every block takes the same decisions from the same values.
-            int64_t items = 0, work = 0;
+            // every block of the die takes the same decisions from the same values.
+            int64_t items = 0, wk = 0;
             const int32_t sl_me = threadIdx.x;
             if (sl_me < active && !s_done[sl_me]) {
-                const SlotArgs &sd = a.slots[sl_me];
+                const SlotArgs &sd = a.slots[slot0 + sl_me];
                 const unsigned long long *c = ctr_buf(sd, round);
                 const int64_t pieces = (int64_t)ld_ctr(c + 0), verts = (int64_t)ld_ctr(c + 1),
                               degsum = (int64_t)ld_ctr(c + 2);
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                     s_dense[sl_me] = dense;
                     const int32_t epb = push_entries_per_block(pieces, degsum);
                     s_epb[sl_me] = epb;
-                    work = dense ? a.gr.ntiles : (pieces + epb - 1) / epb;
+                    wk = dense ? a.gr.ntiles : (pieces + epb - 1) / epb;
                     // bitmap words of F_{i-1} to clear: sparse through its queue
                     // when that is cheaper than a dense pass
                     const bool sparse = nprev * 4 < sd.nwords;
@@ -308,9 +310,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                     const int64_t clears = round == 0 ? 0
                                            : (sparse ? (nprev + BLOCK - 1) / BLOCK
                                                      : (sd.nwords + CLEAR_WORDS - 1) / CLEAR_WORDS);
-                    items = work + clears;
-                    if (blockIdx.x == 0) {
-                        long long *st = a.stats + 5 * (int64_t)(wave0 + sl_me);
+                    items = wk + clears;
+                    if (dix == 0) {
+                        long long *st = a.stats + 5 * (int64_t)group_of(sl_me);
                         st[0] += 1;
                         st[dense ? 2 : 1] += 1;
                         st[3] += verts;
@@ -318,7 +320,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                     }
                 }
                 if (verts == 0) s_done[sl_me] = 1;
-                s_work[sl_me] = work;
+                s_work[sl_me] = wk;
                 s_nq[sl_me] = pieces;
                 s_nprev[sl_me] = nprev;
             } else if (sl_me < active) {
@@ -326,8 +328,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
             }
             // items of the slots, in slot order (active <= MAX_SLOTS <= BLOCK)
             int total_work;
-            const int wpos = block_exclusive_scan(work > 0 ? 1 : 0, tmp, &total_work);
-            (void)wpos;
+            block_exclusive_scan(wk > 0 ? 1 : 0, tmp, &total_work);
             {
                 // 64-bit prefix of the item counts over the first `active` threads
                 const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -342,22 +343,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                 if (threadIdx.x == 0) {
                     s_pref[0] = 0;
                     s_stop = total_work == 0 ? 1 : (round > a.max_rounds ? 2 : 0);
-                    if (s_stop == 2 && blockIdx.x == 0)
+                    if (s_stop == 2 && dix == 0)
                         __hip_atomic_store(a.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
             __syncthreads();
             if (s_stop) break;
             // the work counter of round i+2 last served round i-1
-            if (blockIdx.x == 0 && threadIdx.x == 0) a.work[(round + 2) % 3] = 0;
-            // blocks take items at a fixed stride of one (or GRAB at a time from
-            // the round's counter), items being slot-major: push chunks or pull
-            // tiles, then bitmap clears
+            if (dix == 0 && threadIdx.x == 0) work[(round + 2) % 3] = 0;
+            // the die's blocks take items at a fixed stride of one (or GRAB at a
+            // time from the round's counter), items being slot-major: push
+            // chunks or pull tiles, then bitmap clears
             const int64_t total = s_pref[active];
-            unsigned long long *wctr = a.work + (round % 3);
+            unsigned long long *wctr = work + (round % 3);
             const int64_t grab = a.schedule == 1 ? GRAB : 1;
             int32_t sl = 0;
-            for (int64_t next = (int64_t)blockIdx.x * grab;; next += (int64_t)nb * grab) {
+            for (int64_t next = (int64_t)dix * grab;; next += (int64_t)dtotal * grab) {
                 if (a.schedule == 1) {
                     if (threadIdx.x == 0) s_grab = (int64_t)atomicAdd(wctr, (unsigned long long)GRAB);
                     __syncthreads();
@@ -371,7 +372,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                     if (item < s_pref[sl]) sl = 0;
                     while (item >= s_pref[sl + 1]) sl++;
                     const int64_t local = item - s_pref[sl];
-                    if (sl != s_cached) load_desc(a, wave0, sl, s_slot, s_group, s_cached);
+                    if (sl != s_cached) load_desc(a, slot0 + sl, group_of(sl), sl, s_slot, s_group, s_cached);
                     if (local >= s_work[sl]) {
                         __syncthreads();
                         clear_item(s_slot, round, s_sparse[sl] != 0, s_nprev[sl], local - s_work[sl]);
@@ -383,14 +384,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                     }
                 }
             }
-            if ((aborted = grid_barrier(a.ctl, die, ndies, a.err, s_abort))) break;
+            if ((aborted = die_barrier(a.ctl, die, dtotal, a.err, s_abort))) break;
         }
         if (aborted) break;
         for (int32_t sl = 0; sl < active; sl++) {
-            load_desc(a, wave0, sl, s_slot, s_group, s_cached);
-            finalize_part<W, WC>(s_slot, a.gr.n, s_group, a.o, gtid, gstride);
+            load_desc(a, slot0 + sl, group_of(sl), sl, s_slot, s_group, s_cached);
+            finalize_part<W, WC>(s_slot, a.gr.n, s_group, a.o, dtid, dstride);
         }
-        if ((aborted = grid_barrier(a.ctl, die, ndies, a.err, s_abort))) break;
+        if ((aborted = die_barrier(a.ctl, die, dtotal, a.err, s_abort))) break;
     }
 }
 

@@ -215,7 +215,7 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
     p.off_src = take(sizeof(int32_t) * (size_t)std::max(1, p.total_sources));
     p.off_slotdesc = take(sizeof(SlotArgs) * MAX_SLOTS);
     p.off_groupdesc = take(sizeof(GroupDesc) * (size_t)p.groups);
-    p.off_ctl = take(sizeof(unsigned int) * CTL_WORDS + 256);
+    p.off_ctl = take(sizeof(unsigned int) * CTL_WORDS + 512);
     p.off_stats = take(sizeof(long long) * 5 * (size_t)p.groups);
     p.off_slots = off;
     size_t sb = 0;
@@ -398,7 +398,7 @@ static cbfs_status run_persistent(const Plan &p, const cbfs_csr *g, uint32_t *di
     a.max_rounds = p.n + 2 * (int64_t)p.R + 4;
     // barrier, error flag and statistics start at zero (plain memsets: this
     // path is never captured into a graph)
-    if ((e = hipMemsetAsync(ws + p.off_ctl, 0, sizeof(unsigned int) * CTL_WORDS + 256, st)) != hipSuccess)
+    if ((e = hipMemsetAsync(ws + p.off_ctl, 0, sizeof(unsigned int) * CTL_WORDS + 512, st)) != hipSuccess)
         return hip_fail("control reset", e);
     if ((e = hipMemsetAsync(ws + p.off_stats, 0, sizeof(long long) * 5 * (size_t)p.groups, st)) != hipSuccess)
         return hip_fail("stats reset", e);
