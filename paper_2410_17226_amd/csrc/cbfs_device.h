@@ -377,14 +377,38 @@ __device__ __forceinline__ void stager_push(Stager<CAP> &st, int32_t v, int32_t 
     atomicAdd(&st.degsum, (unsigned long long)deg);
 }
 
-// Block-uniform call (every thread).
+// Block-uniform call (every thread).  With sort, the staged vertices are
+// first ordered by id (bitonic sort in LDS), so a later chunk of the queue
+// covers nearby vertices whose state, distance and plane words share cache
+// lines (worth it for low-degree frontiers, where those words dominate).
 template <int CAP>
 __device__ __forceinline__ void stager_flush(Stager<CAP> &st, const int32_t *row_ptr, int64_t *q_next,
-                                             unsigned long long *ctr_next)
+                                             unsigned long long *ctr_next, bool sort = false)
 {
+    static_assert((CAP & (CAP - 1)) == 0, "the stager sorts a power-of-two array");
     __syncthreads();
     const int cnt = st.count;
     if (cnt == 0) return;
+    if (sort) {
+        int np2 = 1;
+        while (np2 < cnt) np2 <<= 1;
+        for (int k = cnt + threadIdx.x; k < np2; k += BLOCK) st.v[k] = INT32_MAX;
+        __syncthreads();
+        for (int k = 2; k <= np2; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < np2; i += BLOCK) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const int32_t x = st.v[i], y = st.v[ixj];
+                        if (((i & k) == 0) ? (x > y) : (x < y)) {
+                            st.v[i] = y;
+                            st.v[ixj] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+    }
     const int per = (cnt + BLOCK - 1) / BLOCK;
     const int lo = threadIdx.x * per < cnt ? threadIdx.x * per : cnt;
     const int hi = lo + per < cnt ? lo + per : cnt;

@@ -187,7 +187,7 @@ __device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &
                 if (any) contribute<W>(sm.st, nxt, bits_next, gr.row_ptr, v[j], x);
             }
             // at most BLOCK * DB <= STAGE_CAP claims per pass
-            stager_flush(sm.st, gr.row_ptr, q_next, ctr_next);
+            stager_flush(sm.st, gr.row_ptr, q_next, ctr_next, true);
         }
         return;
     }
