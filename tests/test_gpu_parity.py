@@ -167,6 +167,26 @@ def test_parity_radius_zero():
         assert_same(gpu, ref, f"R=0 {tun}")
 
 
+@pytest.mark.parametrize("tun", TUNINGS, ids=TUNING_IDS)
+def test_parity_degenerate_graphs(tun):
+    """A single vertex (no arcs at all: empty pull tiles), one edge, and a
+    triangle with every vertex a source, in every direction mode."""
+    import paper_2410_17226_amd as P
+    cases = [(1, [], [0], [0, 1]), (2, [(0, 1)], [0, 1], [0, 2]), (3, [(0, 1), (1, 2), (0, 2)], [1, 0, 2], [0, 3]),
+             (2, [(0, 1)], [1, 0], [0, 1, 2])]
+    for n, edges, srcs, cptr in cases:
+        e = np.array(edges, np.int64).reshape(-1, 2)
+        rp, col, _ = P.build_csr(n, e[:, 0], e[:, 1], flags=7)
+        orp, ocol, _ = oracle.clean_csr(n, e[:, 0], e[:, 1], flags=7)
+        assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+        cp = np.array(cptr, np.int32)
+        src = np.array(srcs, np.int32)
+        for R in (0, 1):
+            gpu = gpu_cbfs(rp, col, cp, src, R, tuning_of(tun))
+            ref = oracle.cbfs(rp, col, cp, src, R=R)
+            assert_same(gpu, ref, f"n={n} edges={edges} R={R}")
+
+
 def workload_inputs(name):
     cfg = configs.WORKLOADS[name]
     n, s, d = configs.raw_graph(name)
