@@ -162,11 +162,13 @@ __host__ __device__ inline int32_t push_entries_per_block(int64_t pieces, int64_
 //   - center not yet seen: dist holds the first round Delta_c any bit of the
 //     cluster arrived; for R >= 2 the bits are stashed at plane i - Delta_c.
 // Any bit whose offset leaves [-R, R] marks the cluster CBFS_E_RADIUS.
+// dold is dist[c][v] as it stood before this call (the caller loads it with
+// the state words; only this call writes it in this round).
 // ---------------------------------------------------------------------------
 template <int WC>
 __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_t c, int32_t v,
                                              int32_t i, const uint64_t *prev, const uint64_t *nw,
-                                             const uint64_t *full)
+                                             const uint64_t *full, uint32_t dold)
 {
     uint64_t any_new = 0, any_prev = 0;
 #pragma unroll
@@ -192,7 +194,7 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
     auto violate = [&]() { atomicExch(o.status + c, E_RADIUS); };
 
     if (prev[0] & 1ull) {
-        const int32_t k = i - (int32_t)(*dslot);
+        const int32_t k = i - (int32_t)dold;
         if (k < 1 || k > R) {
             violate();
         } else if (R > 1) {
@@ -201,7 +203,7 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
         return;
     }
     if (nw[0] & 1ull) {
-        const int32_t jc = any_prev ? i - (int32_t)(*dslot) : 0;
+        const int32_t jc = any_prev ? i - (int32_t)dold : 0;
         if (jc < 0 || jc > R) {
             violate();
             return;
@@ -234,7 +236,7 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
     if (!any_prev) {
         *dslot = (uint32_t)i;
     } else {
-        j = i - (int32_t)(*dslot);
+        j = i - (int32_t)dold;
     }
     if (j < 0 || j >= R) {
         violate();
@@ -258,6 +260,9 @@ __device__ __forceinline__ void vertex_phase_cluster(const SlotArgs &s, const Gr
 {
     const uint64_t *cp = cur_buf(s, round) + (size_t)u * W + j * WC;
     uint64_t *sp = s.seen + (size_t)u * W + j * WC;
+    // the cluster's distance word is requested with the state words, so the
+    // encode does not wait for a second round trip
+    const uint32_t dold = o.dist[(size_t)(g.c0 + j) * (size_t)n + (size_t)u];
     uint64_t cu[WC], sv[WC], nw[WC];
     uint64_t any = 0;
 #pragma unroll
@@ -274,7 +279,7 @@ __device__ __forceinline__ void vertex_phase_cluster(const SlotArgs &s, const Gr
         if constexpr (NXT_OR)
             if (nw[x]) or64(nxt_buf(s, round) + (size_t)u * W + j * WC + x, nw[x]);
     }
-    emit_cluster<WC>(o, n, g.c0 + j, u, round, sv, nw, g.full + j * WC);
+    emit_cluster<WC>(o, n, g.c0 + j, u, round, sv, nw, g.full + j * WC, dold);
 }
 
 // The vertex phase of u for every cluster of the group, one after another.
