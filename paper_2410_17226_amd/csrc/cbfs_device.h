@@ -254,9 +254,12 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
 // Seen_{i-1}(u) from cur and seen.  With NXT_OR, nxt(u) receives the new bits
 // by atomic OR so that nxt(u) covers Seen_i(u) by the end of the round;
 // without it the caller stores nxt(u) itself (it owns u's row in this round).
+// With active false the words are still read (so a caller can request them
+// before it knows u is in F_i) and nothing is written.
 template <int W, int WC, bool NXT_OR>
 __device__ __forceinline__ void vertex_phase_cluster(const SlotArgs &s, const GroupDesc &g, const OutArgs &o,
-                                                     int64_t n, int32_t round, int32_t u, int32_t j)
+                                                     int64_t n, int32_t round, int32_t u, int32_t j,
+                                                     bool active = true)
 {
     const uint64_t *cp = cur_buf(s, round) + (size_t)u * W + j * WC;
     uint64_t *sp = s.seen + (size_t)u * W + j * WC;
@@ -265,11 +268,12 @@ __device__ __forceinline__ void vertex_phase_cluster(const SlotArgs &s, const Gr
     const uint32_t dold = o.dist[(size_t)(g.c0 + j) * (size_t)n + (size_t)u];
     uint64_t cu[WC], sv[WC], nw[WC];
     uint64_t any = 0;
+    const uint64_t am = active ? ~0ull : 0ull;  // a value mask, so the loads stay ahead of the test
 #pragma unroll
     for (int x = 0; x < WC; x++) {
         cu[x] = cp[x];
         sv[x] = sp[x];
-        nw[x] = cu[x] & ~sv[x];
+        nw[x] = cu[x] & ~sv[x] & am;
         any |= nw[x];
     }
     if (!any) return;

@@ -479,13 +479,15 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         finish_local(pend, cv, acc);
     }
     // vertex phase of the rows whose end item is in this tile, one thread per
-    // (row, cluster): the threads of a row read its words together
+    // (row, cluster): the threads of a row read its words together, with the
+    // frontier word (membership only gates the writes)
     constexpr int CPV = W / WC;
     for (int32_t idx = threadIdx.x; idx < (r1 - r0) * CPV; idx += BLOCK) {
         const int32_t v = r0 + idx / CPV, j = idx % CPV;
-        if (j >= g.nc || !((bits_cur[v >> 6] >> (v & 63)) & 1ull)) continue;
-        if (v < T.loc_lo) vertex_phase_cluster<W, WC, true>(s, g, o, gr.n, round, v, j);  // tile-crossing row
-        else vertex_phase_cluster<W, WC, false>(s, g, o, gr.n, round, v, j);
+        if (j >= g.nc) continue;
+        const bool in_f = (bits_cur[v >> 6] >> (v & 63)) & 1ull;
+        if (v < T.loc_lo) vertex_phase_cluster<W, WC, true>(s, g, o, gr.n, round, v, j, in_f);  // tile-crossing row
+        else vertex_phase_cluster<W, WC, false>(s, g, o, gr.n, round, v, j, in_f);
     }
     __syncthreads();
 }
