@@ -86,7 +86,7 @@ def main():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-clusters", type=int, default=2, help="clusters in the CPU oracle sample")
+    ap.add_argument("--cpu-clusters", type=int, default=6, help="clusters in the CPU oracle sample")
     ap.add_argument("--no-query", action="store_true")
     ap.add_argument("--workload", default="rmat22", choices=["rmat22", "grid4096", "chunglu25"],
                     help="batch workload (the default is the headline one)")
