@@ -308,17 +308,51 @@ __device__ __forceinline__ void pull_claim(PullSmem<W> &sm, const PullTile &T, i
     atomicOr(reinterpret_cast<unsigned long long *>(&sm.claimed[(v >> 6) - T.wbase]), 1ull << (v & 63));
 }
 
-__device__ __forceinline__ uint64_t shfl_up64(uint64_t x, int d)
+// A 64-bit DPP move: lanes whose source is outside the row, and rows left out
+// of ROW_MASK, read 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x)
 {
-    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 64);
-    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 64);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROW_MASK, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROW_MASK, 0xF, true);
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint64_t shfl64(uint64_t x, int src)
+// Inclusive segmented OR-scan over the wave: afterwards lane i holds the OR of
+// lanes [first, i], where first <= i is the first lane of i's segment and
+// segments are runs of consecutive lanes.  Shifts by 1, 2, 4, 8 inside each
+// row of 16 lanes (DPP row_shr), then the ends of rows 0 and 2 into rows 1 and
+// 3 (row_bcast:15), then the end of row 1 into rows 2 and 3 (row_bcast:31):
+// all in VALU, no LDS permutes.
+template <int W>
+__device__ __forceinline__ void seg_or_scan(uint64_t (&x)[W], int lane, int first)
 {
-    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src, 64);
-    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, 64);
+    auto level = [&](auto ctrl, auto rmask, bool take) {
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            const uint64_t y = dpp64<decltype(ctrl)::value, decltype(rmask)::value>(x[w]);
+            x[w] |= take ? y : 0ull;
+        }
+    };
+    using c1 = std::integral_constant<int, 0x111>;
+    using c2 = std::integral_constant<int, 0x112>;
+    using c4 = std::integral_constant<int, 0x114>;
+    using c8 = std::integral_constant<int, 0x118>;
+    using b15 = std::integral_constant<int, 0x142>;
+    using b31 = std::integral_constant<int, 0x143>;
+    using all = std::integral_constant<int, 0xF>;
+    level(c1{}, all{}, lane - 1 >= first);
+    level(c2{}, all{}, lane - 2 >= first);
+    level(c4{}, all{}, lane - 4 >= first);
+    level(c8{}, all{}, lane - 8 >= first);
+    level(b15{}, std::integral_constant<int, 0xA>{}, (lane & ~15) - 1 >= first);
+    level(b31{}, std::integral_constant<int, 0xC>{}, 31 >= first);
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int src)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
     return ((uint64_t)hi << 32) | lo;
 }
 
@@ -591,36 +625,29 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         const int32_t k = base + lane;
         const bool in = k < wb;
         const int32_t rk = in ? (int32_t)sm.wv.arow[k] : 0;  // a valid row index on every lane
-        const int32_t ro = in ? rk : 0x7fffffff;              // lanes past the range match no row
         const bool active = in && !((sm.wv.fin[rk >> 6] >> (rk & 63)) & 1ull);
+        const int32_t re = in ? (int32_t)sm.rend[rk] : 0;
         uint64_t x[W];
 #pragma unroll
         for (int w = 0; w < W; w++) x[w] = 0;
         if (__ballot(active)) {
             const int32_t u = active ? gr.col[e0 + k] : r0;
             const uint64_t hm = active ? ~0ull : 0ull;
+            // the lane where this row's arcs begin in this step (lanes of one
+            // row are consecutive); a lane past the range is its own segment
+            const int32_t rs = rstart_off(rk) - base;
+            const int first = in ? (rs > 0 ? rs : 0) : lane;
             load_words<W>(cur + (size_t)u * W, x);
 #pragma unroll
             for (int w = 0; w < W; w++) x[w] &= hm;
-            // segmented OR-scan: lanes of one row are consecutive
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int32_t rup = __shfl_up(ro, d, 64);
-                const bool take = lane >= d && rup == ro;
-#pragma unroll
-                for (int w = 0; w < W; w++) {
-                    const uint64_t y = shfl_up64(x[w], d);
-                    if (take) x[w] |= y;
-                }
-            }
+            seg_or_scan<W>(x, lane, first);
         }
-        const int32_t rdown = __shfl_down(ro, 1, 64);
-        const bool tail = in && (lane == 63 || rdown != ro || k + 1 == wb);
-        if (tail && ro == crow) {
+        // the last lane of a row's run in this step
+        const bool tail = in && (lane == 63 || k + 1 == wb || k + 1 == re);
+        if (tail && rk == crow) {
 #pragma unroll
             for (int w = 0; w < W; w++) x[w] |= cacc[w];
         }
-        const int32_t re = in ? (int32_t)sm.rend[rk] : 0;
         const bool closes = tail && k + 1 == re;            // the row's last arc in the tile
         const bool leaves = tail && !closes && k + 1 == wb;  // open past this wave's range
         const bool carries = tail && !closes && !leaves;     // only lane 63
@@ -638,10 +665,10 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
             for (int w = 0; w < W; w++) sm.wv.out_acc[wv][w] = x[w];
         }
         // carry into the next step, and stop gathering for a completed row
-        if (__shfl((int)carries, 63, 64)) {
-            crow = __shfl(ro, 63, 64);
+        if (__builtin_amdgcn_readlane((int)carries, 63)) {
+            crow = __builtin_amdgcn_readlane(rk, 63);
 #pragma unroll
-            for (int w = 0; w < W; w++) cacc[w] = shfl64(x[w], 63);
+            for (int w = 0; w < W; w++) cacc[w] = readlane64(x[w], 63);
             if (lane == 0) {
                 uint64_t cv[W];
                 load_words<W>(cur + (size_t)(r0 + crow) * W, cv);
