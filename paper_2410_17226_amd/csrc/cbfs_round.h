@@ -588,15 +588,12 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     }
     __syncthreads();
 
-    // a row whose every contribution from this tile is in x
-    auto finish_row = [&](int32_t k, const uint64_t (&x)[W]) {
-        bool nz = false;
-#pragma unroll
-        for (int w = 0; w < W; w++) nz |= x[w] != 0;
-        if (!nz) return;
+    const int32_t wa = (int32_t)(((int64_t)tile_edges * wv) / WAVES);
+    const int32_t wb = (int32_t)(((int64_t)tile_edges * (wv + 1)) / WAVES);
+    // a row whose every contribution from this tile is in x; cv holds cur(v)
+    auto finish_row_cv = [&](int32_t k, const uint64_t (&x)[W], uint64_t (&cv)[W]) {
         const int32_t v = r0 + k;
-        uint64_t cv[W], acc[W];
-        load_words<W>(cur + (size_t)v * W, cv);
+        uint64_t acc[W];
         bool any = false;
 #pragma unroll
         for (int w = 0; w < W; w++) {
@@ -614,14 +611,38 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
             pull_claim(sm, T, v);
         }
     };
-
-    const int32_t wa = (int32_t)(((int64_t)tile_edges * wv) / WAVES);
-    const int32_t wb = (int32_t)(((int64_t)tile_edges * (wv + 1)) / WAVES);
-    int32_t crow = -1;  // row carried from the wave's previous step (wave-uniform)
-    uint64_t cacc[W];
+    auto finish_row = [&](int32_t k, const uint64_t (&x)[W]) {
+        bool nz = false;
 #pragma unroll
-    for (int w = 0; w < W; w++) cacc[w] = 0;
-    for (int32_t base = wa; base < wb; base += 64) {
+        for (int w = 0; w < W; w++) nz |= x[w] != 0;
+        if (!nz) return;
+        uint64_t cv[W];
+        load_words<W>(cur + (size_t)(r0 + k) * W, cv);
+        finish_row_cv(k, x, cv);
+    };
+    // a row's share of this wave's range ends with x: finished here, or left
+    // for the merge below (begun in an earlier wave's range, or open past it)
+    auto close_row = [&](int32_t k, const uint64_t (&x)[W]) {
+        if (rstart_off(k) >= wa) {
+            finish_row(k, x);
+        } else {
+            sm.wv.pend_row[wv] = k;
+#pragma unroll
+            for (int w = 0; w < W; w++) sm.wv.pend_acc[wv][w] = x[w];
+        }
+    };
+    auto leave_row = [&](int32_t k, const uint64_t (&x)[W]) {
+        sm.wv.out_row[wv] = k;
+#pragma unroll
+        for (int w = 0; w < W; w++) sm.wv.out_acc[wv][w] = x[w];
+    };
+
+    int32_t crow = -1;  // row carried from the wave's previous step (wave-uniform)
+    uint64_t cacc[W], ccv[W];  // its OR so far, and its cur words (requested when it began to carry)
+#pragma unroll
+    for (int w = 0; w < W; w++) cacc[w] = ccv[w] = 0;
+    for (int32_t base = wa; base < wb;) {
+        int32_t next = base + 64;
         const int32_t k = base + lane;
         const bool in = k < wb;
         const int32_t rk = in ? (int32_t)sm.wv.arow[k] : 0;  // a valid row index on every lane
@@ -651,35 +672,44 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         const bool closes = tail && k + 1 == re;            // the row's last arc in the tile
         const bool leaves = tail && !closes && k + 1 == wb;  // open past this wave's range
         const bool carries = tail && !closes && !leaves;     // only lane 63
-        if (closes) {
-            if (rstart_off(rk) >= wa) {
-                finish_row(rk, x);
-            } else {
-                sm.wv.pend_row[wv] = rk;
-#pragma unroll
-                for (int w = 0; w < W; w++) sm.wv.pend_acc[wv][w] = x[w];
-            }
-        } else if (leaves) {
-            sm.wv.out_row[wv] = rk;
-#pragma unroll
-            for (int w = 0; w < W; w++) sm.wv.out_acc[wv][w] = x[w];
-        }
-        // carry into the next step, and stop gathering for a completed row
+        if (closes) close_row(rk, x);
+        else if (leaves) leave_row(rk, x);
+        // carry into the next step; a carried row found complete adds nothing
+        // more, so the wave closes it now and jumps past its remaining arcs
         if (__builtin_amdgcn_readlane((int)carries, 63)) {
-            crow = __builtin_amdgcn_readlane(rk, 63);
+            const int32_t nrow = __builtin_amdgcn_readlane(rk, 63);
 #pragma unroll
             for (int w = 0; w < W; w++) cacc[w] = readlane64(x[w], 63);
-            if (lane == 0) {
-                uint64_t cv[W];
-                load_words<W>(cur + (size_t)(r0 + crow) * W, cv);
+            if (nrow != crow) {
+                crow = nrow;
+                load_words<W>(cur + (size_t)(r0 + crow) * W, ccv);  // tested from the next step on
+            } else {
                 bool f = true;
 #pragma unroll
-                for (int w = 0; w < W; w++) f &= (cacc[w] | cv[w]) == full[w];
-                if (f) atomicOr(reinterpret_cast<unsigned long long *>(&sm.wv.fin[crow >> 6]), 1ull << (crow & 63));
+                for (int w = 0; w < W; w++) f &= (cacc[w] | ccv[w]) == full[w];
+                if (f) {
+                    const int32_t cre = (int32_t)sm.rend[crow];
+                    if (lane == 0) {
+                        atomicOr(reinterpret_cast<unsigned long long *>(&sm.wv.fin[crow >> 6]), 1ull << (crow & 63));
+                        if (cre > wb) {
+                            leave_row(crow, cacc);
+                        } else if (rstart_off(crow) >= wa) {
+                            uint64_t cv[W];
+#pragma unroll
+                            for (int w = 0; w < W; w++) cv[w] = ccv[w];
+                            finish_row_cv(crow, cacc, cv);
+                        } else {
+                            close_row(crow, cacc);  // pending: merged after the loop
+                        }
+                    }
+                    next = cre <= wb ? cre : wb;
+                    crow = -1;
+                }
             }
         } else {
             crow = -1;
         }
+        base = next;
     }
     __syncthreads();
     // rows split between waves: the closing wave's share plus the earlier ones;
