@@ -35,7 +35,7 @@ namespace cbfs {
 constexpr int BLOCK = 256;          // threads per block (4 waves of 64)
 constexpr int WAVES = BLOCK / 64;
 constexpr int PIECE = 256;          // max arcs per frontier work item (push)
-constexpr int TILE_ITEMS = 8192;    // merge-path items (rows + arcs) per pull block
+constexpr int TILE_ITEMS = 6144;    // merge-path items (rows + arcs) per pull block (LDS for 5 blocks per CU)
 constexpr int IPT = TILE_ITEMS / BLOCK;
 static_assert(TILE_ITEMS + 2 <= 65535, "pull tiles stage row ends as 16-bit offsets");
 constexpr int PULL_CLAIM_WORDS = TILE_ITEMS / 64 + 2;  // bitmap words spanned by a tile's rows
