@@ -259,7 +259,7 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
 template <int W, int WC, bool NXT_OR>
 __device__ __forceinline__ void vertex_phase_cluster(const SlotArgs &s, const GroupDesc &g, const OutArgs &o,
                                                      int64_t n, int32_t round, int32_t u, int32_t j,
-                                                     bool active = true)
+                                                     bool active = true, bool copy_nxt = false)
 {
     const uint64_t *cp = cur_buf(s, round) + (size_t)u * W + j * WC;
     uint64_t *sp = s.seen + (size_t)u * W + j * WC;
@@ -275,6 +275,12 @@ __device__ __forceinline__ void vertex_phase_cluster(const SlotArgs &s, const Gr
         sv[x] = sp[x];
         nw[x] = cu[x] & ~sv[x] & am;
         any |= nw[x];
+    }
+    if (copy_nxt) {
+        // nxt(u) = Seen_i(u) for a row of F_i whose arc phase found nothing new
+        uint64_t *np = nxt_buf(s, round) + (size_t)u * W + j * WC;
+#pragma unroll
+        for (int x = 0; x < WC; x++) np[x] = cu[x];
     }
     if (!any) return;
 #pragma unroll

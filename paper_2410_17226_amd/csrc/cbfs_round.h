@@ -21,6 +21,8 @@ template <int W>
 struct PullSmem {
     uint16_t rend[TILE_ITEMS + 2];           // row_end of the tile's rows minus tile_edge (clamped)
     uint64_t claimed[PULL_CLAIM_WORDS];      // F_{i+1} bits of the tile's rows, from word tile_row >> 6
+    uint64_t fin[PULL_ROW_WORDS];            // rows whose set is complete (bit: row - tile_row)
+    uint64_t stored[PULL_ROW_WORDS];         // local rows whose nxt the arc phase stored
     int tmp[WAVES + 1];
     unsigned long long degsum;
     long long base;
@@ -28,8 +30,6 @@ struct PullSmem {
         uint64_t part[BLOCK][W];             // walk: partial sets of rows shared by threads, by first thread
         struct {
             uint16_t arow[TILE_ITEMS];       // row of each of the tile's arcs, minus tile_row
-            uint64_t fin[PULL_ROW_WORDS];    // rows whose set is complete (bit: row - tile_row)
-            uint64_t stored[PULL_ROW_WORDS]; // local rows whose nxt the arc phase stored
             uint64_t out_acc[WAVES][W];      // a wave's share of the row still open at its range end
             uint64_t pend_acc[WAVES][W];     // a wave's share of a row it closes that began earlier
             int32_t out_row[WAVES], pend_row[WAVES];
@@ -403,18 +403,20 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
 #pragma unroll
     for (int w = 0; w < W; w++) full[w] = g.full[w];
 
+    // a local row with new bits stores nxt(v) here; a row of F_i without any
+    // gets nxt(v) = Seen_i(v) in the vertex pass
     auto finish_local = [&](int32_t v, const uint64_t (&cv)[W], const uint64_t (&acc)[W]) {
         bool any = false;
 #pragma unroll
         for (int w = 0; w < W; w++) any |= acc[w] != 0;
-        const bool in_f = (bits_cur[v >> 6] >> (v & 63)) & 1ull;
-        if (in_f || any) {
-            uint64_t nv[W];
+        if (!any) return;
+        uint64_t nv[W];
 #pragma unroll
-            for (int w = 0; w < W; w++) nv[w] = cv[w] | acc[w];
-            store_words<W>(nxt + (size_t)v * W, nv);
-        }
-        if (any) pull_claim(sm, T, v);
+        for (int w = 0; w < W; w++) nv[w] = cv[w] | acc[w];
+        store_words<W>(nxt + (size_t)v * W, nv);
+        const int32_t k = v - r0;
+        atomicOr(reinterpret_cast<unsigned long long *>(&sm.stored[k >> 6]), 1ull << (k & 63));
+        pull_claim(sm, T, v);
     };
 
     // a local row owned here whose first arcs other threads scanned: its own
@@ -425,6 +427,16 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         const int32_t rend = rend_of(row);
         const int32_t budget = my_end - rel;
         const int32_t seg_end = rend < edge + budget ? rend : edge + budget;
+        if ((sm.fin[(row - r0) >> 6] >> ((row - r0) & 63)) & 1ull) {
+            // complete when the round began: nothing to gather, nothing new
+            rel += seg_end - edge;
+            edge = seg_end;
+            if (!(edge == rend && rel < my_end)) break;
+            rel++;
+            row++;
+            rstart = rend;
+            continue;
+        }
         uint64_t cv[W], acc[W];
         // software pipeline: the row's own set, the first two batches'
         // neighbour ids and the first batch's frontier words are requested
@@ -512,16 +524,23 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         for (int w = 0; w < W; w++) acc[w] = slot[w];
         finish_local(pend, cv, acc);
     }
+    __syncthreads();
     // vertex phase of the rows whose end item is in this tile, one thread per
     // (row, cluster): the threads of a row read its words together, with the
-    // frontier word (membership only gates the writes)
+    // frontier word (membership only gates the writes); a local row of F_i
+    // the arc phase did not store gets nxt(v) = Seen_i(v)
     constexpr int CPV = W / WC;
     for (int32_t idx = threadIdx.x; idx < (r1 - r0) * CPV; idx += BLOCK) {
         const int32_t v = r0 + idx / CPV, j = idx % CPV;
         if (j >= g.nc) continue;
         const bool in_f = (bits_cur[v >> 6] >> (v & 63)) & 1ull;
-        if (v < T.loc_lo) vertex_phase_cluster<W, WC, true>(s, g, o, gr.n, round, v, j, in_f);  // tile-crossing row
-        else vertex_phase_cluster<W, WC, false>(s, g, o, gr.n, round, v, j, in_f);
+        const int32_t k = v - r0;
+        if (v < T.loc_lo) {
+            vertex_phase_cluster<W, WC, true>(s, g, o, gr.n, round, v, j, in_f);  // tile-crossing row
+        } else {
+            const bool copy = in_f && !((sm.stored[k >> 6] >> (k & 63)) & 1ull);
+            vertex_phase_cluster<W, WC, false>(s, g, o, gr.n, round, v, j, in_f, copy);
+        }
     }
     __syncthreads();
 }
@@ -537,16 +556,11 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     uint64_t *bits_next = bits_buf(s, (round + 1) % 3);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int32_t r0 = T.r0, e0 = T.e0, r1 = T.r1, tile_rows = T.tile_rows, tile_edges = T.tile_edges;
-    const int32_t nrw = (tile_rows + 1 + 63) >> 6;
     uint64_t full[W];
 #pragma unroll
     for (int w = 0; w < W; w++) full[w] = g.full[w];
 
     for (int32_t k = threadIdx.x; k < tile_edges; k += BLOCK) sm.wv.arow[k] = 0;
-    for (int32_t k = threadIdx.x; k < nrw; k += BLOCK) {
-        sm.wv.fin[k] = 0;
-        sm.wv.stored[k] = 0;
-    }
     if (threadIdx.x < WAVES) {
         sm.wv.out_row[threadIdx.x] = -1;
         sm.wv.pend_row[threadIdx.x] = -1;
@@ -554,7 +568,7 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     __syncthreads();
     // row start offset of row r0 + k (negative for a row begun before the tile)
     auto rstart_off = [&](int32_t k) { return k == 0 ? T.start_r0 - e0 : (int32_t)sm.rend[k - 1]; };
-    // row starts scattered for the arc -> row map; complete rows marked
+    // row starts scattered for the arc -> row map
     for (int32_t k = threadIdx.x; k <= tile_rows; k += BLOCK) {
         const int32_t r = r0 + k;
         if ((int64_t)r >= gr.n) continue;
@@ -562,12 +576,6 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         const int32_t a = so > 0 ? so : 0;
         const int32_t b = (int32_t)sm.rend[k] < tile_edges ? (int32_t)sm.rend[k] : tile_edges;
         if (a < b) sm.wv.arow[a] = (uint16_t)k;
-        uint64_t cv[W];
-        load_words<W>(cur + (size_t)r * W, cv);
-        bool f = true;
-#pragma unroll
-        for (int w = 0; w < W; w++) f &= cv[w] == full[w];
-        if (f) atomicOr(reinterpret_cast<unsigned long long *>(&sm.wv.fin[k >> 6]), 1ull << (k & 63));
     }
     __syncthreads();
     {
@@ -605,7 +613,7 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
 #pragma unroll
             for (int w = 0; w < W; w++) cv[w] |= acc[w];
             store_words<W>(nxt + (size_t)v * W, cv);
-            atomicOr(reinterpret_cast<unsigned long long *>(&sm.wv.stored[k >> 6]), 1ull << (k & 63));
+            atomicOr(reinterpret_cast<unsigned long long *>(&sm.stored[k >> 6]), 1ull << (k & 63));
             pull_claim(sm, T, v);
         } else if (merge_global<W>(nxt, bits_next, v, acc)) {
             pull_claim(sm, T, v);
@@ -646,7 +654,7 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         const int32_t k = base + lane;
         const bool in = k < wb;
         const int32_t rk = in ? (int32_t)sm.wv.arow[k] : 0;  // a valid row index on every lane
-        const bool active = in && !((sm.wv.fin[rk >> 6] >> (rk & 63)) & 1ull);
+        const bool active = in && !((sm.fin[rk >> 6] >> (rk & 63)) & 1ull);
         const int32_t re = in ? (int32_t)sm.rend[rk] : 0;
         uint64_t x[W];
 #pragma unroll
@@ -690,7 +698,7 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
                 if (f) {
                     const int32_t cre = (int32_t)sm.rend[crow];
                     if (lane == 0) {
-                        atomicOr(reinterpret_cast<unsigned long long *>(&sm.wv.fin[crow >> 6]), 1ull << (crow & 63));
+                        atomicOr(reinterpret_cast<unsigned long long *>(&sm.fin[crow >> 6]), 1ull << (crow & 63));
                         if (cre > wb) {
                             leave_row(crow, cacc);
                         } else if (rstart_off(crow) >= wa) {
@@ -756,11 +764,8 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         if (v < T.loc_lo) {
             vertex_phase_cluster<W, WC, true>(s, g, o, gr.n, round, v, j);  // tile-crossing row
         } else {
-            if (!((sm.wv.stored[k >> 6] >> (k & 63)) & 1ull)) {
-#pragma unroll
-                for (int x = 0; x < WC; x++) nxt[(size_t)v * W + j * WC + x] = cur[(size_t)v * W + j * WC + x];
-            }
-            vertex_phase_cluster<W, WC, false>(s, g, o, gr.n, round, v, j);
+            const bool copy = !((sm.stored[k >> 6] >> (k & 63)) & 1ull);
+            vertex_phase_cluster<W, WC, false>(s, g, o, gr.n, round, v, j, true, copy);
         }
     }
     __syncthreads();
@@ -779,6 +784,28 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     }
     for (int32_t k = threadIdx.x; k < T.nclaim; k += BLOCK) sm.claimed[k] = 0;
     if (threadIdx.x == 0) sm.degsum = 0;
+    // rows whose set is already complete gather nothing: each wave tests 64
+    // consecutive rows (coalesced row words) and writes their bitmap word
+    {
+        const uint64_t *cur = cur_buf(s, round);
+        const int lane = threadIdx.x & 63;
+        for (int32_t kb = (int32_t)(threadIdx.x >> 6) * 64; kb <= T.tile_rows; kb += WAVES * 64) {
+            const int32_t k = kb + lane;
+            bool f = false;
+            if (k <= T.tile_rows && (int64_t)(T.r0 + k) < gr.n) {
+                uint64_t cv[W];
+                load_words<W>(cur + (size_t)(T.r0 + k) * W, cv);
+                f = true;
+#pragma unroll
+                for (int w = 0; w < W; w++) f &= cv[w] == g.full[w];
+            }
+            const uint64_t word = __ballot(f);
+            if (lane == 0) {
+                sm.fin[kb >> 6] = word;
+                sm.stored[kb >> 6] = 0;
+            }
+        }
+    }
     if (form == PULL_WAVE) pull_wave<W, WC>(sm, s, gr, g, o, round, T);
     else pull_walk<W, WC>(sm, s, gr, g, o, round, T);
 
