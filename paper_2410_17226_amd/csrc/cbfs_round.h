@@ -646,7 +646,7 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     };
 
     int32_t crow = -1;  // row carried from the wave's previous step (wave-uniform)
-    uint64_t cacc[W], ccv[W];  // its OR so far, and its cur words (requested when it began to carry)
+    uint64_t cacc[W], ccv[W];  // its OR so far, and its cur words
 #pragma unroll
     for (int w = 0; w < W; w++) cacc[w] = ccv[w] = 0;
     for (int32_t base = wa; base < wb;) {
@@ -656,6 +656,15 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         const int32_t rk = in ? (int32_t)sm.wv.arow[k] : 0;  // a valid row index on every lane
         const bool active = in && !((sm.fin[rk >> 6] >> (rk & 63)) & 1ull);
         const int32_t re = in ? (int32_t)sm.rend[rk] : 0;
+        // a row that will carry out of this step and was not carried into it:
+        // its words go out with this step's gathers, so the completeness test
+        // at the step's end already covers its first 64 arcs
+        {
+            const int32_t r63 = __builtin_amdgcn_readlane(rk, 63);
+            const int32_t re63 = __builtin_amdgcn_readlane(re, 63);
+            if (base + 64 < wb && re63 != base + 64 && r63 != crow)
+                load_words<W>(cur + (size_t)(r0 + r63) * W, ccv);
+        }
         uint64_t x[W];
 #pragma unroll
         for (int w = 0; w < W; w++) x[w] = 0;
@@ -685,13 +694,10 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         // carry into the next step; a carried row found complete adds nothing
         // more, so the wave closes it now and jumps past its remaining arcs
         if (__builtin_amdgcn_readlane((int)carries, 63)) {
-            const int32_t nrow = __builtin_amdgcn_readlane(rk, 63);
+            crow = __builtin_amdgcn_readlane(rk, 63);
 #pragma unroll
             for (int w = 0; w < W; w++) cacc[w] = readlane64(x[w], 63);
-            if (nrow != crow) {
-                crow = nrow;
-                load_words<W>(cur + (size_t)(r0 + crow) * W, ccv);  // tested from the next step on
-            } else {
+            {
                 bool f = true;
 #pragma unroll
                 for (int w = 0; w < W; w++) f &= (cacc[w] | ccv[w]) == full[w];
