@@ -180,6 +180,10 @@ typedef struct {
     float gamma;               /* a group's first pull round runs in the wave form (every
                                   neighbour's set OR-ed, no frontier-bitmap test) when
                                   sum deg(F) > gamma * m; 0 = auto (0.5), < 0 = never   */
+    int32_t hub_arcs;          /* host-loop mode: a push round whose frontier has at most
+                                  256 vertices and at least hub_arcs arcs runs with
+                                  blocks that own target ranges (sets merged in LDS, one
+                                  store per target); 0 = auto (65536), < 0 = never      */
 } cbfs_tuning;
 
 /* Bytes of device workspace cbfs_run_batch needs for these arguments. */

@@ -42,6 +42,8 @@ constexpr int PULL_CLAIM_WORDS = TILE_ITEMS / 64 + 2;  // bitmap words spanned b
 constexpr int PULL_ROW_WORDS = (TILE_ITEMS + 1 + 63) / 64;  // one bit per row of a tile
 static_assert(PULL_CLAIM_WORDS <= BLOCK, "one claimed word per thread at a pull tile's flush");
 enum { PULL_WALK = 0, PULL_WAVE = 1 };  // forms of the pull round
+constexpr int HUB_MAX = 256;        // frontier vertices of a range-owned push round at most
+constexpr int HUB_RANGE = 256;      // target vertices owned by one range-owned push block
 constexpr int STAGE_CAP = 1024;     // LDS frontier staging capacity per push/seed block
 // arcs per pass when each push thread walks its own entry (wide groups hold
 // fewer neighbour sets in registers)

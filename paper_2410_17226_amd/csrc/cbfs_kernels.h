@@ -45,6 +45,11 @@ hipError_t launch_seed(int W, int WC, const SlotArgs &s, const GraphArgs &gr, co
                        const int32_t *sources, const int32_t *cluster_ptr, hipStream_t st);
 hipError_t launch_push(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                        const OutArgs &o, int32_t round, int64_t nq, int64_t degsum, hipStream_t st);
+// Push round for a frontier of at most HUB_MAX vertices (nq queue entries):
+// lists them into hubs[0 .. hubs[HUB_MAX]) (HUB_MAX + 1 ints of device
+// memory), then one block per HUB_RANGE target vertices.
+hipError_t launch_push_hub(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
+                           const OutArgs &o, int32_t round, int64_t nq, int32_t *hubs, hipStream_t st);
 hipError_t launch_pull(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                        const OutArgs &o, int32_t round, int32_t form, hipStream_t st);
 hipError_t launch_finalize(int W, int WC, const SlotArgs &s, int64_t n, const GroupDesc &g, const OutArgs &o,

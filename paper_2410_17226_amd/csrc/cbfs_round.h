@@ -230,6 +230,118 @@ __device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &
 }
 
 // ---------------------------------------------------------------------------
+// Round i, push direction, for a frontier of at most HUB_MAX vertices whose
+// arcs are many (on skewed graphs the sources of round 0 are hubs whose
+// neighbour lists overlap).  Each block owns HUB_RANGE consecutive target
+// vertices.  For every frontier vertex u it finds the slice of u's sorted
+// neighbour list inside its range (two binary searches), ORs Seen_i(u) into
+// LDS sets of its targets, and then writes nxt(v) once per target with a plain
+// store: the global set-union atomics of the arc-parallel push become LDS
+// atomics, and a target hit by many frontier vertices is written once.  A
+// target's claim is a bit of a frontier-bitmap word the block owns.  The
+// vertex phase of the frontier vertices in the range runs here as well.
+// hubs[0 .. hubs[HUB_MAX]) lists the frontier's vertices.
+// ---------------------------------------------------------------------------
+static_assert(HUB_RANGE == BLOCK && HUB_MAX <= BLOCK, "one owned target and one frontier vertex per thread");
+static_assert(HUB_RANGE % 64 == 0, "a block owns whole frontier-bitmap words");
+
+template <int W>
+struct HubSmem {
+    uint64_t acc[HUB_RANGE * W];  // OR of the frontier sets arriving at each owned target
+    int32_t hub[HUB_MAX], hlo[HUB_MAX], hoff[HUB_MAX + 1];
+    int tmp[WAVES + 1];
+    Stager<HUB_RANGE> st;
+};
+
+template <int W, int WC>
+__device__ void push_hub_block(HubSmem<W> &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
+                               const OutArgs &o, int32_t round, const int32_t *hubs, int64_t b)
+{
+    const int64_t v0 = b * HUB_RANGE;
+    if (v0 >= gr.n) return;  // block-uniform
+    const int32_t v1 = (int32_t)(v0 + HUB_RANGE < gr.n ? v0 + HUB_RANGE : gr.n);
+    const uint64_t *cur = cur_buf(s, round);
+    uint64_t *nxt = nxt_buf(s, round);
+    const uint64_t *bits_cur = bits_buf(s, round % 3);
+    uint64_t *bits_next = bits_buf(s, (round + 1) % 3);
+    const int32_t nh = hubs[HUB_MAX];
+    __syncthreads();
+    stager_init(sm.st);
+    for (int k = threadIdx.x; k < HUB_RANGE * W; k += BLOCK) sm.acc[k] = 0;
+    // the slice of each frontier vertex's neighbour list inside [v0, v1)
+    int len = 0;
+    if ((int)threadIdx.x < nh) {
+        const int32_t u = hubs[threadIdx.x];
+        const int32_t rs = gr.row_ptr[u], re = gr.row_ptr[u + 1];
+        auto lower = [&](int32_t lo, int32_t hi, int32_t key) {
+            while (lo < hi) {
+                const int32_t mid = lo + ((hi - lo) >> 1);
+                if (gr.col[mid] < key) lo = mid + 1;
+                else hi = mid;
+            }
+            return lo;
+        };
+        const int32_t a = lower(rs, re, (int32_t)v0);
+        len = lower(a, re, v1) - a;
+        sm.hub[threadIdx.x] = u;
+        sm.hlo[threadIdx.x] = a;
+    }
+    int total;
+    const int off = block_exclusive_scan(len, sm.tmp, &total);
+    if ((int)threadIdx.x < nh) sm.hoff[threadIdx.x] = off;
+    __syncthreads();
+    // the slices' arcs spread over the threads; a slice's arcs are consecutive
+    for (int idx = threadIdx.x; idx < total; idx += BLOCK) {
+        int lo = 0, hi = nh;  // the last frontier vertex whose slice starts at or before idx
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (sm.hoff[mid] <= idx) lo = mid;
+            else hi = mid;
+        }
+        const int32_t v = gr.col[sm.hlo[lo] + (idx - sm.hoff[lo])];
+        uint64_t x[W];
+        load_words<W>(cur + (size_t)sm.hub[lo] * W, x);
+        unsigned long long *a = reinterpret_cast<unsigned long long *>(sm.acc + (size_t)(v - v0) * W);
+#pragma unroll
+        for (int w = 0; w < W; w++)
+            if (x[w]) atomicOr(a + w, x[w]);
+    }
+    __syncthreads();
+    // one owned target per thread: nxt(v) = Seen_i(v) | arrivals, stored once;
+    // v joins F_{i+1} when the arrivals hold bits it lacked
+    const int32_t v = (int32_t)v0 + (int32_t)threadIdx.x;
+    bool claimed = false, in_f = false;
+    if (v < v1) {
+        uint64_t a[W];
+        bool any = false;
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            a[w] = sm.acc[threadIdx.x * W + w];
+            any |= a[w] != 0;
+        }
+        in_f = (bits_cur[v >> 6] >> (v & 63)) & 1ull;
+        if (any || in_f) {
+            uint64_t cv[W];
+            load_words<W>(cur + (size_t)v * W, cv);
+            bool gained = false;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                gained |= (a[w] & ~cv[w]) != 0;
+                cv[w] |= a[w];
+            }
+            if (gained || in_f) store_words<W>(nxt + (size_t)v * W, cv);
+            claimed = gained;
+        }
+    }
+    const uint64_t word = __ballot(claimed);
+    if ((threadIdx.x & 63) == 0 && word)
+        atomicOr(reinterpret_cast<unsigned long long *>(bits_next + ((v0 >> 6) + (threadIdx.x >> 6))), word);
+    if (claimed) stager_push(sm.st, v, gr.row_ptr[v + 1] - gr.row_ptr[v]);
+    if (in_f) vertex_phase<W, WC, false>(s, g, o, gr.n, round, v);
+    stager_flush(sm.st, gr.row_ptr, q_buf(s, round + 1), ctr_buf(s, round + 1), true);
+}
+
+// ---------------------------------------------------------------------------
 // Round i, pull direction (EdgeMap-Dense), one merge-path tile of TILE_ITEMS
 // items (arcs and row ends) of the CSR: rows [tile_row, next tile_row) end in
 // the tile, and its arcs are [tile_edge, next tile_edge).  The tile's row ends

@@ -104,6 +104,7 @@ struct Plan {
     int32_t mode = CBFS_MODE_PERSISTENT;
     float alpha = 15.0f, beta = 20.0f, gamma = 0.5f;
     int32_t force_pull = 0;
+    int64_t hub_arcs = 65536;  // range-owned push from this many frontier arcs; <= 0: never
     int32_t blocks_per_cu = 0, schedule = 0;
     int32_t ntiles = 0;
     int64_t nwords = 0;
@@ -111,7 +112,7 @@ struct Plan {
     int32_t total_sources = 0;
     // workspace offsets
     size_t off_tiles_row = 0, off_tiles_edge = 0, off_cptr = 0, off_src = 0;
-    size_t off_slotdesc = 0, off_groupdesc = 0, off_ctl = 0, off_stats = 0;
+    size_t off_slotdesc = 0, off_groupdesc = 0, off_ctl = 0, off_stats = 0, off_hub = 0;
     size_t off_slots = 0, slot_bytes = 0;
     size_t total = 0;
 };
@@ -175,6 +176,7 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
         if (t->beta != 0.0f) p.beta = t->beta;
         if (t->gamma != 0.0f) p.gamma = t->gamma;
         p.force_pull = t->force_pull;
+        if (t->hub_arcs != 0) p.hub_arcs = t->hub_arcs;
         if (t->concurrent_groups < 0 || t->concurrent_groups > MAX_SLOTS)
             return fail(CBFS_E_ARG, "cbfs_tuning: concurrent_groups outside [0, 64]");
         want_slots = t->concurrent_groups;
@@ -217,6 +219,7 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
     p.off_groupdesc = take(sizeof(GroupDesc) * (size_t)p.groups);
     p.off_ctl = take(sizeof(unsigned int) * CTL_WORDS + 512);
     p.off_stats = take(sizeof(long long) * 5 * (size_t)p.groups);
+    p.off_hub = take(sizeof(int32_t) * (HUB_MAX + 1));
     p.off_slots = off;
     size_t sb = 0;
     sb += 3 * align_up(sizeof(uint64_t) * (size_t)p.n * p.W);
@@ -358,7 +361,12 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
                 pulls == 0 && p.gamma > 0.0f && (double)degsum > (double)p.gamma * (double)p.m ? PULL_WAVE
                                                                                                : PULL_WALK;
             if (dense) pulls++;
+            // a push from a few vertices with many arcs: targets owned by blocks
+            const bool hub = !dense && p.hub_arcs > 0 && verts <= HUB_MAX && degsum >= p.hub_arcs;
             if (dense) e = PROF(CBFS_KERNEL_PULL, st, launch_pull(p.W, p.WC, s, gr, gd, o, round, form, st));
+            else if (hub)
+                e = PROF(CBFS_KERNEL_PUSH, st,
+                         launch_push_hub(p.W, p.WC, s, gr, gd, o, round, pieces, (int32_t *)(ws + p.off_hub), st));
             else e = PROF(CBFS_KERNEL_PUSH, st, launch_push(p.W, p.WC, s, gr, gd, o, round, pieces, degsum, st));
             if (e != hipSuccess) return hip_fail(dense ? "pull" : "push", e);
         }
@@ -686,6 +694,10 @@ extern "C" cbfs_status cbfs_autotune(const cbfs_csr *g, const cbfs_batch *b, con
     if (make_plan(g, &tu.sample, &tu.best, pb, false) == CBFS_OK && pb.mode == CBFS_MODE_PERSISTENT)
         if ((rc = step([](cbfs_tuning &t, int32_t v) { t.concurrent_groups = v; }, kTuneSlots)) != CBFS_OK)
             return rc;
+    if (pb.mode == CBFS_MODE_HOST_LOOP) {
+        const int32_t hubs[] = {16384, 65536, -1};
+        if ((rc = step([](cbfs_tuning &t, int32_t v) { t.hub_arcs = v; }, hubs)) != CBFS_OK) return rc;
+    }
     if (tu.best_ms < 0.f) return fail(CBFS_E_WORKSPACE, "cbfs_autotune: no candidate fits the workspace");
     *best = tu.best;
     if (num_trials) *num_trials = tu.count;
