@@ -93,6 +93,14 @@ __global__ __launch_bounds__(BLOCK) void k_push_hub(SlotArgs s, GraphArgs gr, Gr
     push_hub_block<W, WC>(sm, s, gr, g, o, round, hubs, blockIdx.x);
 }
 
+__global__ __launch_bounds__(BLOCK) void k_bits_to_queue(SlotArgs s, GraphArgs gr, int32_t round)
+{
+    __shared__ int tmp[WAVES + 1];
+    __shared__ unsigned long long red[2];
+    __shared__ long long base;
+    bits_to_queue_block(s, gr, round, tmp, red, &base);
+}
+
 template <int W, int WC>
 __global__ __launch_bounds__(BLOCK) void k_pull(SlotArgs s, GraphArgs gr, GroupDesc g, OutArgs o, int32_t round,
                                                int32_t form)
@@ -489,6 +497,9 @@ hipError_t launch_push_hub(int W, int WC, const SlotArgs &s, const GraphArgs &gr
     if (e != hipSuccess) return e;
     const int64_t blocks = std::max<int64_t>((gr.n + HUB_RANGE - 1) / HUB_RANGE, clear_blocks(s.nwords));
     CBFS_DISPATCH(W, WC, (k_push_hub<W, WC><<<(unsigned)blocks, BLOCK, 0, st>>>(s, gr, g, o, round, hubs)));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t per_block = (int64_t)BLOCK * BQ_VPT;
+    k_bits_to_queue<<<(unsigned)((gr.n + per_block - 1) / per_block), BLOCK, 0, st>>>(s, gr, round);
     return hipGetLastError();
 }
 

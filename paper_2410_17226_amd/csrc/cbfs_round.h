@@ -238,8 +238,10 @@ __device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &
 // LDS sets of its targets, and then writes nxt(v) once per target with a plain
 // store: the global set-union atomics of the arc-parallel push become LDS
 // atomics, and a target hit by many frontier vertices is written once.  A
-// target's claim is a bit of a frontier-bitmap word the block owns.  The
-// vertex phase of the frontier vertices in the range runs here as well.
+// target's claim is a bit of a frontier-bitmap word the block owns; the
+// F_{i+1} queue is built from the bitmap afterwards (bits_to_queue_block), so
+// the many short blocks do not contend for the queue counters.  The vertex
+// phase of the frontier vertices in the range runs here as well.
 // hubs[0 .. hubs[HUB_MAX]) lists the frontier's vertices.
 // ---------------------------------------------------------------------------
 static_assert(HUB_RANGE == BLOCK && HUB_MAX <= BLOCK, "one owned target and one frontier vertex per thread");
@@ -250,7 +252,6 @@ struct HubSmem {
     uint64_t acc[HUB_RANGE * W];  // OR of the frontier sets arriving at each owned target
     int32_t hub[HUB_MAX], hlo[HUB_MAX], hoff[HUB_MAX + 1];
     int tmp[WAVES + 1];
-    Stager<HUB_RANGE> st;
 };
 
 template <int W, int WC>
@@ -265,26 +266,42 @@ __device__ void push_hub_block(HubSmem<W> &sm, const SlotArgs &s, const GraphArg
     const uint64_t *bits_cur = bits_buf(s, round % 3);
     uint64_t *bits_next = bits_buf(s, (round + 1) % 3);
     const int32_t nh = hubs[HUB_MAX];
-    __syncthreads();
-    stager_init(sm.st);
     for (int k = threadIdx.x; k < HUB_RANGE * W; k += BLOCK) sm.acc[k] = 0;
     // the slice of each frontier vertex's neighbour list inside [v0, v1)
     int len = 0;
     if ((int)threadIdx.x < nh) {
         const int32_t u = hubs[threadIdx.x];
         const int32_t rs = gr.row_ptr[u], re = gr.row_ptr[u + 1];
-        auto lower = [&](int32_t lo, int32_t hi, int32_t key) {
-            while (lo < hi) {
-                const int32_t mid = lo + ((hi - lo) >> 1);
-                if (gr.col[mid] < key) lo = mid + 1;
-                else hi = mid;
+        // the first arcs with id >= v0 and >= v1: both searches at once, each
+        // round probing 4 points per bracket (8 loads in flight), so a list of
+        // d arcs takes about log5(d) dependent rounds
+        int32_t lo[2] = {rs, rs}, hi[2] = {re, re};
+        const int32_t key[2] = {(int32_t)v0, v1};
+        while (lo[0] < hi[0] || lo[1] < hi[1]) {
+            int32_t q[2][4], x[2][4];
+#pragma unroll
+            for (int h = 0; h < 2; h++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    q[h][j] = lo[h] + (int32_t)(((int64_t)(hi[h] - lo[h]) * (j + 1)) / 5);
+                    x[h][j] = lo[h] < hi[h] ? gr.col[q[h][j]] : 0;
+                }
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                if (lo[h] >= hi[h]) continue;
+                int32_t nlo = lo[h], nhi = hi[h];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    if (x[h][j] < key[h]) nlo = q[h][j] + 1 > nlo ? q[h][j] + 1 : nlo;
+                    else nhi = q[h][j] < nhi ? q[h][j] : nhi;
+                }
+                lo[h] = nlo;
+                hi[h] = nhi;
             }
-            return lo;
-        };
-        const int32_t a = lower(rs, re, (int32_t)v0);
-        len = lower(a, re, v1) - a;
+        }
+        len = lo[1] - lo[0];
         sm.hub[threadIdx.x] = u;
-        sm.hlo[threadIdx.x] = a;
+        sm.hlo[threadIdx.x] = lo[0];
     }
     int total;
     const int off = block_exclusive_scan(len, sm.tmp, &total);
@@ -336,9 +353,62 @@ __device__ void push_hub_block(HubSmem<W> &sm, const SlotArgs &s, const GraphArg
     const uint64_t word = __ballot(claimed);
     if ((threadIdx.x & 63) == 0 && word)
         atomicOr(reinterpret_cast<unsigned long long *>(bits_next + ((v0 >> 6) + (threadIdx.x >> 6))), word);
-    if (claimed) stager_push(sm.st, v, gr.row_ptr[v + 1] - gr.row_ptr[v]);
     if (in_f) vertex_phase<W, WC, false>(s, g, o, gr.n, round, v);
-    stager_flush(sm.st, gr.row_ptr, q_buf(s, round + 1), ctr_buf(s, round + 1), true);
+}
+
+// The F_{i+1} queue and its counters from the F_{i+1} bitmap, after a round
+// that set only bitmap bits.  Each thread takes BQ_VPT consecutive vertices
+// (a slice of one bitmap word and their row_ptr entries, loaded together),
+// one counter update per block; entries come out in vertex order.
+constexpr int BQ_VPT = 16;
+static_assert(64 % BQ_VPT == 0, "a thread's vertices lie in one bitmap word");
+
+__device__ void bits_to_queue_block(const SlotArgs &s, const GraphArgs &gr, int32_t round, int *tmp,
+                                    unsigned long long *red /*[2]*/, long long *base)
+{
+    const int64_t v0 = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * BQ_VPT;
+    uint32_t m = 0;  // this thread's claimed vertices, bit k for v0 + k
+    if (v0 < gr.n) m = (uint32_t)(bits_buf(s, (round + 1) % 3)[v0 >> 6] >> (v0 & 63)) & ((1u << BQ_VPT) - 1);
+    int32_t rp[BQ_VPT + 1];
+    int pieces = 0;
+    unsigned long long degs = 0;
+    if (m) {
+        // claimed vertices are < n, so row_ptr[v0 .. v0 + BQ_VPT] is needed
+        // only up to row_ptr[n]
+#pragma unroll
+        for (int k = 0; k <= BQ_VPT; k++) rp[k] = v0 + k <= gr.n ? gr.row_ptr[v0 + k] : 0;
+#pragma unroll
+        for (int k = 0; k < BQ_VPT; k++)
+            if ((m >> k) & 1u) {
+                const int32_t d = rp[k + 1] - rp[k];
+                pieces += pieces_of(d);
+                degs += (unsigned long long)d;
+            }
+    }
+    if (threadIdx.x == 0) red[0] = red[1] = 0;
+    int total;
+    const int off = block_exclusive_scan(pieces, tmp, &total);  // its barriers order the clear above
+    if (m) {
+        atomicAdd(&red[0], (unsigned long long)__popc(m));
+        atomicAdd(&red[1], degs);
+    }
+    __syncthreads();
+    if (total == 0) return;  // block-uniform
+    if (threadIdx.x == 0) {
+        unsigned long long *ctr = ctr_buf(s, round + 1);
+        *base = (long long)atomicAdd(ctr + 0, (unsigned long long)total);
+        atomicAdd(ctr + 1, red[0]);
+        atomicAdd(ctr + 2, red[1]);
+    }
+    __syncthreads();
+    if (!m) return;
+    int64_t *dst = q_buf(s, round + 1) + *base + off;
+#pragma unroll
+    for (int k = 0; k < BQ_VPT; k++)
+        if ((m >> k) & 1u) {
+            const int pc = pieces_of(rp[k + 1] - rp[k]);
+            for (int p = 0; p < pc; p++) *dst++ = ((int64_t)p << 32) | (int64_t)(uint32_t)(v0 + k);
+        }
 }
 
 // ---------------------------------------------------------------------------
