@@ -368,6 +368,50 @@ __device__ __forceinline__ int block_exclusive_max(int x, int *tmp /*[WAVES+1]*/
 // appended to the global queue with one atomic per flush, expanded into their
 // PIECE-sized work items (offsets from a block scan at flush time).
 // ---------------------------------------------------------------------------
+// Queue entries of vertices with many pieces (hubs) are written by the whole
+// block rather than by the one thread that holds the vertex: such a vertex
+// goes to this LDS list (BIG_CAP at most per flush, the rest its thread
+// writes), and big_write spreads its pieces over the threads.
+constexpr int BIG_PIECES = 8;  // more pieces than this: written by the block
+constexpr int BIG_CAP = 32;
+struct BigList {
+    int32_t v[BIG_CAP], pc[BIG_CAP];
+    long long at[BIG_CAP];
+    int n;
+};
+
+// Entries (p << 32 | v), p < pc, at q[at ..]: by this thread, or listed for
+// the block.  big.n must have been zeroed before a barrier that precedes this.
+__device__ __forceinline__ void put_pieces(BigList &big, int64_t *q, long long at, int32_t v, int pc)
+{
+    if (pc > BIG_PIECES) {
+        const int slot = atomicAdd(&big.n, 1);
+        if (slot < BIG_CAP) {
+            big.v[slot] = v;
+            big.pc[slot] = pc;
+            big.at[slot] = at;
+            return;
+        }
+    }
+    for (int p = 0; p < pc; p++) q[at + p] = ((int64_t)p << 32) | (int64_t)(uint32_t)v;
+}
+
+// Block-uniform: the listed vertices' entries, every thread taking a share;
+// leaves the list empty (the trailing barrier orders the reset before reuse).
+__device__ __forceinline__ void big_write(BigList &big, int64_t *q)
+{
+    __syncthreads();
+    const int nb = big.n < BIG_CAP ? big.n : BIG_CAP;
+    for (int i = 0; i < nb; i++) {
+        const int32_t v = big.v[i];
+        const long long at = big.at[i];
+        for (int p = threadIdx.x; p < big.pc[i]; p += BLOCK) q[at + p] = ((int64_t)p << 32) | (int64_t)(uint32_t)v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) big.n = 0;
+    __syncthreads();
+}
+
 template <int CAP>
 struct Stager {
     int32_t v[CAP];
@@ -375,6 +419,7 @@ struct Stager {
     unsigned long long degsum;
     long long base;
     int tmp[WAVES + 1];
+    BigList big;
 };
 
 template <int CAP>
@@ -383,6 +428,7 @@ __device__ __forceinline__ void stager_init(Stager<CAP> &st)
     if (threadIdx.x == 0) {
         st.count = 0;
         st.degsum = 0;
+        st.big.n = 0;
     }
 }
 
@@ -442,13 +488,14 @@ __device__ __forceinline__ void stager_flush(Stager<CAP> &st, const int32_t *row
         atomicAdd(ctr_next + 2, st.degsum);
     }
     __syncthreads();
-    int64_t *dst = q_next + st.base + off;
+    long long at = st.base + off;
     for (int k = lo; k < hi; k++) {
         const int32_t v = st.v[k];
         const int pc = pieces_of(row_ptr[v + 1] - row_ptr[v]);
-        for (int p = 0; p < pc; p++) *dst++ = ((int64_t)p << 32) | (int64_t)(uint32_t)v;
+        put_pieces(st.big, q_next, at, v, pc);
+        at += pc;
     }
-    __syncthreads();
+    big_write(st.big, q_next);
     if (threadIdx.x == 0) {
         st.count = 0;
         st.degsum = 0;

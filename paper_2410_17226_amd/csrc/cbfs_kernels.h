@@ -51,7 +51,10 @@ hipError_t launch_push(int W, int WC, const SlotArgs &s, const GraphArgs &gr, co
 hipError_t launch_push_hub(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                            const OutArgs &o, int32_t round, int64_t nq, int32_t *hubs, hipStream_t st);
 hipError_t launch_pull(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                       const OutArgs &o, int32_t round, int32_t form, hipStream_t st);
+                       const OutArgs &o, int32_t round, int32_t form, bool queue, hipStream_t st);
+// The queue of F_round from its bitmap (after rounds that left only the
+// bitmap and the counters).
+hipError_t launch_build_queue(const SlotArgs &s, const GraphArgs &gr, int32_t round, hipStream_t st);
 hipError_t launch_finalize(int W, int WC, const SlotArgs &s, int64_t n, const GroupDesc &g, const OutArgs &o,
                            hipStream_t st);
 // Blocks of the persistent kernel on the current device: per_cu per compute

@@ -93,21 +93,19 @@ __global__ __launch_bounds__(BLOCK) void k_push_hub(SlotArgs s, GraphArgs gr, Gr
     push_hub_block<W, WC>(sm, s, gr, g, o, round, hubs, blockIdx.x);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_bits_to_queue(SlotArgs s, GraphArgs gr, int32_t round)
+__global__ __launch_bounds__(BLOCK) void k_bits_to_queue(SlotArgs s, GraphArgs gr, int32_t fround, int32_t what)
 {
-    __shared__ int tmp[WAVES + 1];
-    __shared__ unsigned long long red[2];
-    __shared__ long long base;
-    bits_to_queue_block(s, gr, round, tmp, red, &base);
+    __shared__ BitsQueueSmem sm;
+    bits_to_queue_block(sm, s, gr, fround, what);
 }
 
 template <int W, int WC>
 __global__ __launch_bounds__(BLOCK) void k_pull(SlotArgs s, GraphArgs gr, GroupDesc g, OutArgs o, int32_t round,
-                                               int32_t form)
+                                               int32_t form, int32_t queue)
 {
     __shared__ PullSmem<W> sm;
     clear_ahead_part(s, round, (int64_t)blockIdx.x * BLOCK + threadIdx.x, (int64_t)gridDim.x * BLOCK);
-    pull_tile<W, WC>(sm, s, gr, g, o, round, blockIdx.x, form);
+    pull_tile<W, WC>(sm, s, gr, g, o, round, blockIdx.x, form, queue != 0);
 }
 
 template <int W, int WC>
@@ -499,14 +497,22 @@ hipError_t launch_push_hub(int W, int WC, const SlotArgs &s, const GraphArgs &gr
     CBFS_DISPATCH(W, WC, (k_push_hub<W, WC><<<(unsigned)blocks, BLOCK, 0, st>>>(s, gr, g, o, round, hubs)));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t per_block = (int64_t)BLOCK * BQ_VPT;
-    k_bits_to_queue<<<(unsigned)((gr.n + per_block - 1) / per_block), BLOCK, 0, st>>>(s, gr, round);
+    k_bits_to_queue<<<(unsigned)((gr.n + per_block - 1) / per_block), BLOCK, 0, st>>>(s, gr, round + 1, BITS_COUNT);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_queue(const SlotArgs &s, const GraphArgs &gr, int32_t round, hipStream_t st)
+{
+    const int64_t per_block = (int64_t)BLOCK * BQ_VPT;
+    k_bits_to_queue<<<(unsigned)((gr.n + per_block - 1) / per_block), BLOCK, 0, st>>>(s, gr, round, BITS_QUEUE);
     return hipGetLastError();
 }
 
 hipError_t launch_pull(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                       const OutArgs &o, int32_t round, int32_t form, hipStream_t st)
+                       const OutArgs &o, int32_t round, int32_t form, bool queue, hipStream_t st)
 {
-    CBFS_DISPATCH(W, WC, (k_pull<W, WC><<<(unsigned)gr.ntiles, BLOCK, 0, st>>>(s, gr, g, o, round, form)));
+    CBFS_DISPATCH(W, WC, (k_pull<W, WC><<<(unsigned)gr.ntiles, BLOCK, 0, st>>>(s, gr, g, o, round, form,
+                                                                                queue ? 1 : 0)));
     return hipGetLastError();
 }
 

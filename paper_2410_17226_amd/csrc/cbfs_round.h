@@ -21,6 +21,7 @@ template <int W>
 struct PullSmem {
     uint16_t rend[TILE_ITEMS + 2];           // row_end of the tile's rows minus tile_edge (clamped)
     uint64_t claimed[PULL_CLAIM_WORDS];      // F_{i+1} bits of the tile's rows, from word tile_row >> 6
+    BigList big;                             // claimed hub rows whose queue entries the block writes
     uint64_t fin[PULL_ROW_WORDS];            // rows whose set is complete (bit: row - tile_row)
     uint64_t stored[PULL_ROW_WORDS];         // local rows whose nxt the arc phase stored
     int tmp[WAVES + 1];
@@ -356,25 +357,39 @@ __device__ void push_hub_block(HubSmem<W> &sm, const SlotArgs &s, const GraphArg
     if (in_f) vertex_phase<W, WC, false>(s, g, o, gr.n, round, v);
 }
 
-// The F_{i+1} queue and its counters from the F_{i+1} bitmap, after a round
-// that set only bitmap bits.  Each thread takes BQ_VPT consecutive vertices
-// (a slice of one bitmap word and their row_ptr entries, loaded together),
-// one counter update per block; entries come out in vertex order.
+// From a frontier bitmap: its counters, or its queue.  After a round that
+// set only bitmap bits (a pull tile or a range-owned push block that does not
+// build the queue), BITS_COUNT adds F_{i+1}'s pieces, vertices and degree sum
+// to its counters (no returned values: nothing waits on the contended
+// counters).  A push round needs the queue: BITS_QUEUE writes the entries of
+// F_i (bitmap bits[i % 3]) into queue[i % 3], taking block offsets from the
+// spare counter ctr(i)[3], and leaves the other counters alone.  Each thread
+// takes BQ_VPT consecutive vertices (a slice of one bitmap word and their
+// row_ptr entries, loaded together); a block's entries are contiguous and in
+// vertex order, and are written with consecutive threads on consecutive
+// entries.
 constexpr int BQ_VPT = 16;
 static_assert(64 % BQ_VPT == 0, "a thread's vertices lie in one bitmap word");
+enum { BITS_COUNT = 0, BITS_QUEUE = 1 };
+struct BitsQueueSmem {
+    int32_t v[BLOCK * BQ_VPT];       // claimed vertices of the block, in order
+    int32_t start[BLOCK * BQ_VPT];   // their first entry, from the block's base
+    int tmp[WAVES + 1];
+    unsigned long long degsum;
+    long long base;
+};
 
-__device__ void bits_to_queue_block(const SlotArgs &s, const GraphArgs &gr, int32_t round, int *tmp,
-                                    unsigned long long *red /*[2]*/, long long *base)
+__device__ void bits_to_queue_block(BitsQueueSmem &sm, const SlotArgs &s, const GraphArgs &gr, int32_t fround,
+                                    int32_t what)
 {
     const int64_t v0 = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * BQ_VPT;
-    uint32_t m = 0;  // this thread's claimed vertices, bit k for v0 + k
-    if (v0 < gr.n) m = (uint32_t)(bits_buf(s, (round + 1) % 3)[v0 >> 6] >> (v0 & 63)) & ((1u << BQ_VPT) - 1);
+    uint32_t m = 0;  // this thread's frontier vertices, bit k for v0 + k
+    if (v0 < gr.n) m = (uint32_t)(bits_buf(s, fround % 3)[v0 >> 6] >> (v0 & 63)) & ((1u << BQ_VPT) - 1);
     int32_t rp[BQ_VPT + 1];
     int pieces = 0;
     unsigned long long degs = 0;
     if (m) {
-        // claimed vertices are < n, so row_ptr[v0 .. v0 + BQ_VPT] is needed
-        // only up to row_ptr[n]
+        // frontier vertices are < n, so row_ptr is read up to row_ptr[n]
 #pragma unroll
         for (int k = 0; k <= BQ_VPT; k++) rp[k] = v0 + k <= gr.n ? gr.row_ptr[v0 + k] : 0;
 #pragma unroll
@@ -385,30 +400,45 @@ __device__ void bits_to_queue_block(const SlotArgs &s, const GraphArgs &gr, int3
                 degs += (unsigned long long)d;
             }
     }
-    if (threadIdx.x == 0) red[0] = red[1] = 0;
-    int total;
-    const int off = block_exclusive_scan(pieces, tmp, &total);  // its barriers order the clear above
-    if (m) {
-        atomicAdd(&red[0], (unsigned long long)__popc(m));
-        atomicAdd(&red[1], degs);
-    }
-    __syncthreads();
+    if (threadIdx.x == 0) sm.degsum = 0;
+    int total, nv;
+    const int off = block_exclusive_scan(pieces, sm.tmp, &total);  // its barriers order the clear above
+    const int vix = block_exclusive_scan(__popc(m), sm.tmp, &nv);
     if (total == 0) return;  // block-uniform
-    if (threadIdx.x == 0) {
-        unsigned long long *ctr = ctr_buf(s, round + 1);
-        *base = (long long)atomicAdd(ctr + 0, (unsigned long long)total);
-        atomicAdd(ctr + 1, red[0]);
-        atomicAdd(ctr + 2, red[1]);
-    }
-    __syncthreads();
-    if (!m) return;
-    int64_t *dst = q_buf(s, round + 1) + *base + off;
-#pragma unroll
-    for (int k = 0; k < BQ_VPT; k++)
-        if ((m >> k) & 1u) {
-            const int pc = pieces_of(rp[k + 1] - rp[k]);
-            for (int p = 0; p < pc; p++) *dst++ = ((int64_t)p << 32) | (int64_t)(uint32_t)(v0 + k);
+    unsigned long long *ctr = ctr_buf(s, fround);
+    if (what == BITS_COUNT) {
+        if (m) atomicAdd(&sm.degsum, degs);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            atomicAdd(ctr + 0, (unsigned long long)total);
+            atomicAdd(ctr + 1, (unsigned long long)nv);
+            atomicAdd(ctr + 2, sm.degsum);
         }
+        return;
+    }
+    if (m) {
+        int at = off, x = vix;
+#pragma unroll
+        for (int k = 0; k < BQ_VPT; k++)
+            if ((m >> k) & 1u) {
+                sm.v[x] = (int32_t)(v0 + k);
+                sm.start[x] = at;
+                at += pieces_of(rp[k + 1] - rp[k]);
+                x++;
+            }
+    }
+    if (threadIdx.x == 0) sm.base = (long long)atomicAdd(ctr + 3, (unsigned long long)total);
+    __syncthreads();
+    int64_t *q = q_buf(s, fround) + sm.base;
+    for (int e = threadIdx.x; e < total; e += BLOCK) {
+        int lo = 0, hi = nv;  // the last vertex whose entries start at or before e
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (sm.start[mid] <= e) lo = mid;
+            else hi = mid;
+        }
+        q[e] = ((int64_t)(e - sm.start[lo]) << 32) | (int64_t)(uint32_t)sm.v[lo];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -959,9 +989,12 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     __syncthreads();
 }
 
+// queue = false: the tile writes F_{i+1}'s bitmap words and adds to its
+// counters without waiting on them; the queue, if a push round needs it, is
+// built from the bitmap afterwards (bits_to_queue_block).
 template <int W, int WC>
 __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                          const OutArgs &o, int32_t round, int32_t t, int32_t form)
+                          const OutArgs &o, int32_t round, int32_t t, int32_t form, bool queue = true)
 {
     const PullTile T = pull_coords(gr, t);
     __syncthreads();
@@ -971,7 +1004,10 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         sm.rend[k] = (uint16_t)(x > T.tile_edges + 1 ? T.tile_edges + 1 : x);
     }
     for (int32_t k = threadIdx.x; k < T.nclaim; k += BLOCK) sm.claimed[k] = 0;
-    if (threadIdx.x == 0) sm.degsum = 0;
+    if (threadIdx.x == 0) {
+        sm.degsum = 0;
+        sm.big.n = 0;
+    }
     // rows whose set is already complete gather nothing: each wave tests 64
     // consecutive rows (coalesced row words) and writes their bitmap word
     {
@@ -1029,19 +1065,30 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     block_exclusive_scan(__popcll(word), sm.tmp, &cnt_total);
     if (total == 0) return;  // block-uniform
     unsigned long long *ctr_next = ctr_buf(s, round + 1);
+    if (!queue) {
+        if (threadIdx.x == 0) {
+            atomicAdd(ctr_next + 0, (unsigned long long)total);
+            atomicAdd(ctr_next + 1, (unsigned long long)cnt_total);
+            atomicAdd(ctr_next + 2, sm.degsum);
+        }
+        return;
+    }
     if (threadIdx.x == 0) {
         sm.base = (long long)atomicAdd(ctr_next + 0, (unsigned long long)total);
         atomicAdd(ctr_next + 1, (unsigned long long)cnt_total);
         atomicAdd(ctr_next + 2, sm.degsum);
     }
     __syncthreads();
-    int64_t *dst = q_buf(s, round + 1) + sm.base + off;
+    int64_t *q = q_buf(s, round + 1);
+    long long at = sm.base + off;
     const int64_t wi = (int64_t)T.wbase + threadIdx.x;
     for (uint64_t x = word; x; x &= x - 1) {
         const int32_t v = (int32_t)(wi * 64 + __builtin_ctzll(x));
         const int pc = pieces_of(deg_of(v));
-        for (int p = 0; p < pc; p++) *dst++ = ((int64_t)p << 32) | (int64_t)(uint32_t)v;
+        put_pieces(sm.big, q, at, v, pc);
+        at += pc;
     }
+    big_write(sm.big, q);
 }
 
 // ---------------------------------------------------------------------------

@@ -334,6 +334,10 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
             return hip_fail("seed", e);
         bool dense = false;
         int32_t pulls = 0;
+        // whether F_round's queue exists: the seed and the arc-parallel push
+        // build it; pull rounds and the range-owned push leave only the bitmap
+        // and the counters, and a push round builds the queue first
+        bool queued = true;
         for (int32_t round = 0;; round++) {
             if (round > max_rounds) return fail(CBFS_E_HIP, "cbfs_run_batch: level loop did not terminate");
             if ((e = hipMemcpyAsync(hc, s.ctr + 4 * (round & 3), 3 * sizeof(unsigned long long),
@@ -363,7 +367,12 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
             if (dense) pulls++;
             // a push from a few vertices with many arcs: targets owned by blocks
             const bool hub = !dense && p.hub_arcs > 0 && verts <= HUB_MAX && degsum >= p.hub_arcs;
-            if (dense) e = PROF(CBFS_KERNEL_PULL, st, launch_pull(p.W, p.WC, s, gr, gd, o, round, form, st));
+            if (!dense && !queued) {
+                if ((e = PROF(CBFS_KERNEL_PUSH, st, launch_build_queue(s, gr, round, st))) != hipSuccess)
+                    return hip_fail("queue", e);
+            }
+            queued = !dense && !hub;
+            if (dense) e = PROF(CBFS_KERNEL_PULL, st, launch_pull(p.W, p.WC, s, gr, gd, o, round, form, false, st));
             else if (hub)
                 e = PROF(CBFS_KERNEL_PUSH, st,
                          launch_push_hub(p.W, p.WC, s, gr, gd, o, round, pieces, (int32_t *)(ws + p.off_hub), st));
