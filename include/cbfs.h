@@ -164,11 +164,13 @@ enum {
 /* Tuning knobs (nullable: all defaults).  No knob changes any output bit. */
 typedef struct {
     int32_t mode;              /* CBFS_MODE_*                                          */
-    int32_t group_words;       /* words per vertex of a cluster group: 0 = auto, else a
-                                  multiple of W in {1,2,4,8,16}                        */
+    int32_t group_words;       /* words per vertex of a cluster group: 0 = auto (8 for
+                                  clusters of <= 64 sources, 16 for larger ones, the
+                                  cluster's words on sparse graphs), else a multiple
+                                  of W in {1,2,4,8,16}                                 */
     int32_t concurrent_groups; /* group slots searched side by side: 0 = auto          */
     int32_t block_size;        /* 0 = auto, else 256                                    */
-    float alpha;               /* pull when |F| + sum deg(F) > m / alpha; 0 = auto;
+    float alpha;               /* pull when |F| + sum deg(F) > m / alpha; 0 = auto (5);
                                   < 0 forces push every round                           */
     float beta;                /* stay pull while |F| > n / beta; 0 = auto              */
     int32_t force_pull;        /* 1: pull every round (testing)                         */

@@ -102,7 +102,7 @@ struct Plan {
     int32_t groups = 0;
     int32_t slots = 1;
     int32_t mode = CBFS_MODE_PERSISTENT;
-    float alpha = 15.0f, beta = 20.0f, gamma = 0.5f;
+    float alpha = 5.0f, beta = 20.0f, gamma = 0.5f;
     int32_t force_pull = 0;
     int64_t hub_arcs = 65536;  // range-owned push from this many frontier arcs; <= 0: never
     int32_t blocks_per_cu = 0, schedule = 0;
@@ -159,10 +159,12 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
     p.R = b->radius;
     p.total_sources = b->cluster_ptr[p.C];
     p.WC = (kmax + 63) / 64;
-    // defaults: wide groups share one CSR pass among many clusters; sparse
-    // (high-diameter) graphs get narrow groups searched side by side
+    // defaults: wide groups share one CSR pass among many clusters (16 words
+    // for clusters of more than 64 sources, 8 for one-word clusters, whose
+    // 16-word pull kernels run at lower occupancy); sparse (high-diameter)
+    // graphs get narrow groups searched side by side
     const bool sparse = p.m < 8 * p.n;
-    p.W = p.WC == 3 ? 3 : (sparse ? p.WC : 8);
+    p.W = p.WC == 3 ? 3 : (sparse ? p.WC : (p.WC >= 2 ? 16 : 8));
     if (p.W < p.WC) p.W = p.WC;
     p.mode = sparse ? CBFS_MODE_PERSISTENT : CBFS_MODE_HOST_LOOP;
     int32_t want_slots = 0;
