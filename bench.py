@@ -106,8 +106,9 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_only}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the batch of clusters shards "
-                                   "across GPUs without communication (see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; a batch of clusters would shard "
+                                   "across GPUs by cluster groups with a replicated CSR and no communication "
+                                   "during the search, which is not built", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch

@@ -1,5 +1,5 @@
 // cbfs_run_batch: argument checks, workspace layout, cluster grouping, and the
-// two drivers of the level loop (Algorithm "Cluster-BFS search from S": init,
+// two ways to run the level loop (Algorithm "Cluster-BFS search from S": init,
 // then rounds of vertex phase + edge phase until the frontier is empty):
 //   - host loop: one launch per round, the frontier counters read back each
 //     round to choose the direction and to stop;
