@@ -62,26 +62,17 @@ __global__ __launch_bounds__(BLOCK) void k_push(SlotArgs s, GraphArgs gr, GroupD
     push_chunk<W, WC>(sm, s, gr, g, o, round, nq, blockIdx.x, epb);
 }
 
-// The frontier's vertices (entries of piece 0) listed in queue order for the
-// range-owned push: hubs[0 .. hubs[HUB_MAX]).  One block.
+// The frontier's vertices (entries of piece 0) listed for the range-owned
+// push: hubs[0 .. hubs[HUB_MAX]), in no particular order (the push does not
+// depend on it); hubs[HUB_MAX] starts at zero and counts the slots.
 __global__ __launch_bounds__(BLOCK) void k_hub_list(SlotArgs s, int32_t round, int64_t nq, int32_t *hubs)
 {
-    __shared__ int tmp[WAVES + 1];
-    const int64_t *q = q_buf(s, round);
-    int base = 0;
-    for (int64_t k0 = 0; k0 < nq; k0 += BLOCK) {
-        const int64_t k = k0 + threadIdx.x;
-        int32_t v = -1;
-        if (k < nq) {
-            const int64_t e = q[k];
-            if ((e >> 32) == 0) v = (int32_t)(e & 0xffffffff);
-        }
-        int total;
-        const int off = block_exclusive_scan(v >= 0 ? 1 : 0, tmp, &total);
-        if (v >= 0 && base + off < HUB_MAX) hubs[base + off] = v;
-        base += total;
-    }
-    if (threadIdx.x == 0) hubs[HUB_MAX] = base < HUB_MAX ? base : HUB_MAX;
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= nq) return;
+    const int64_t e = q_buf(s, round)[k];
+    if ((e >> 32) != 0) return;
+    const int slot = atomicAdd(hubs + HUB_MAX, 1);
+    if (slot < HUB_MAX) hubs[slot] = (int32_t)(e & 0xffffffff);
 }
 
 template <int W, int WC>
@@ -490,9 +481,13 @@ hipError_t launch_push(int W, int WC, const SlotArgs &s, const GraphArgs &gr, co
 hipError_t launch_push_hub(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                            const OutArgs &o, int32_t round, int64_t nq, int32_t *hubs, hipStream_t st)
 {
-    k_hub_list<<<1, BLOCK, 0, st>>>(s, round, nq, hubs);
-    hipError_t e = hipGetLastError();
+    // the host guarantees at most HUB_MAX frontier vertices
+    hipError_t e = hipMemsetAsync(hubs + HUB_MAX, 0, sizeof(int32_t), st);
     if (e != hipSuccess) return e;
+    if (nq > 0) {
+        k_hub_list<<<(unsigned)((nq + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(s, round, nq, hubs);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     const int64_t blocks = std::max<int64_t>((gr.n + HUB_RANGE - 1) / HUB_RANGE, clear_blocks(s.nwords));
     CBFS_DISPATCH(W, WC, (k_push_hub<W, WC><<<(unsigned)blocks, BLOCK, 0, st>>>(s, gr, g, o, round, hubs)));
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -266,7 +266,7 @@ __device__ void push_hub_block(HubSmem<W> &sm, const SlotArgs &s, const GraphArg
     uint64_t *nxt = nxt_buf(s, round);
     const uint64_t *bits_cur = bits_buf(s, round % 3);
     uint64_t *bits_next = bits_buf(s, (round + 1) % 3);
-    const int32_t nh = hubs[HUB_MAX];
+    const int32_t nh = hubs[HUB_MAX] < HUB_MAX ? hubs[HUB_MAX] : HUB_MAX;
     for (int k = threadIdx.x; k < HUB_RANGE * W; k += BLOCK) sm.acc[k] = 0;
     // the slice of each frontier vertex's neighbour list inside [v0, v1)
     int len = 0;
