@@ -172,3 +172,45 @@ def test_autotune_argument_errors_before_launch():
     assert rc == -4  # CBFS_E_TOO_MANY_SOURCES
     assert lib.cbfs_autotune_workspace_size(ctypes.byref(g), ctypes.byref(b), 0) > 0
 
+
+
+_C_TYPES = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "float": ctypes.c_float,
+            "size_t": ctypes.c_size_t}
+
+
+def header_structs():
+    """Field names and C types of every typedef'd struct in the header."""
+    text = open(os.path.join(ROOT, "include", "cbfs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(cbfs_[a-z_]+)\s*;", text, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = " ".join(decl.split())
+            if not decl:
+                continue
+            m = re.match(r"(?:const )?([a-z_0-9]+)\s*(\*?)\s*(.*)", decl)
+            ctype, ptr, names = m.groups()
+            for fname in names.split(","):
+                fname = fname.strip()
+                star = ptr or fname.startswith("*")
+                fields.append((fname.lstrip("*").strip(), "ptr" if star else ctype))
+        out[name] = fields
+    return out
+
+
+@pytest.mark.parametrize("cname,pyname", [("cbfs_csr", "_Csr"), ("cbfs_batch", "_Batch"),
+                                          ("cbfs_tuning", "_Tuning"), ("cbfs_trial", "_Trial"),
+                                          ("cbfs_run_stats", "_RunStats"), ("cbfs_labels", "_Labels")])
+def test_binding_structs_mirror_the_header(cname, pyname):
+    """Every ctypes mirror has the header's fields, in order, with the same C types."""
+    want = header_structs()[cname]
+    got = getattr(B, pyname)._fields_
+    assert [n for n, _ in got] == [n for n, _ in want], cname
+    for (n, t), (_, c) in zip(got, want):
+        if c == "ptr":
+            assert t is ctypes.c_void_p, (cname, n)
+        elif c in _C_TYPES:
+            assert t is _C_TYPES[c], (cname, n, c)
+        else:  # a nested struct of the header
+            assert t.__name__ == {"cbfs_tuning": "_Tuning"}.get(c, c), (cname, n, c)
