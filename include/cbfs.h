@@ -124,8 +124,11 @@ cbfs_status cbfs_select_clusters(int64_t n, const int32_t *row_ptr, const int32_
  *                           o in [-R, R]; all zero where dist is CBFS_UNREACHED
  *   cluster_status[c]     = CBFS_OK, or CBFS_E_RADIUS when some source of c
  *                           lies at an offset outside [-R, R] at some vertex
- *                           (or reaches a vertex the center does not); the
- *                           outputs of such a cluster are unspecified.
+ *                           (or reaches a vertex the center does not), or
+ *                           CBFS_E_HIP when the persistent kernel stopped
+ *                           early (see cbfs_last_run_stats).  A cluster whose
+ *                           status is not CBFS_OK has dist = CBFS_UNREACHED
+ *                           and every mask word 0 at every vertex.
  * W (words per mask) = ceil(max_c k_c / 64) over the batch.  By the Fact and
  * Corollary of Section 3.1 every offset is bounded by the source's distance to
  * the center, so R >= that distance for every source guarantees CBFS_OK on a
@@ -196,14 +199,28 @@ size_t cbfs_run_batch_workspace_size(const cbfs_csr *g, const cbfs_batch *b, con
  *   masks          device [C][2R+1][n][W] uint64 output
  *   cluster_status device [C]             int32 output
  *   workspace      device, workspace_bytes >= cbfs_run_batch_workspace_size(...)
- * Asynchronous on `stream` in CBFS_MODE_PERSISTENT; CBFS_MODE_HOST_LOOP waits
- * on the stream once per round.  Errors: CBFS_E_ARG, CBFS_E_RANGE,
- * CBFS_E_DUP_SOURCE, CBFS_E_TOO_MANY_SOURCES, CBFS_E_WORKSPACE (before any
- * launch); CBFS_E_HIP.
+ * Ordering: everything is enqueued on `stream`.  In CBFS_MODE_PERSISTENT the
+ * call returns without waiting for the device: the batch tables go up from a
+ * pinned staging buffer the library owns (a ring of buffers, each reused
+ * once its upload has run; only when all of them are still in flight does a
+ * call wait for the oldest upload).  CBFS_MODE_HOST_LOOP waits on the stream
+ * once per round to read the frontier counters.  The outputs are complete
+ * when the stream reaches the end of the call's work.
+ * Errors: CBFS_E_ARG, CBFS_E_RANGE, CBFS_E_DUP_SOURCE, CBFS_E_TOO_MANY_SOURCES,
+ * CBFS_E_WORKSPACE (before any launch); CBFS_E_HIP, CBFS_E_NOMEM.
  */
 cbfs_status cbfs_run_batch(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *t,
                            uint32_t *dist, uint64_t *masks, int32_t *cluster_status,
                            void *workspace, size_t workspace_bytes, void *stream);
+
+/* Releases the host resources the library holds (the pinned staging buffers
+ * and their events, the pinned counter words of the host loop, the calling
+ * thread's profiling events), after waiting for the uploads still in flight.
+ * Later calls allocate them again as needed.  Meant for process exit, while
+ * the HIP runtime is still up (the Python binding registers it with atexit):
+ * the library then holds no HIP object when the runtime is torn down.
+ * Errors: CBFS_E_HIP (a release call failed; the rest are still released). */
+cbfs_status cbfs_release(void);
 
 /* ------------------------------------------------------------------------ *
  * Diagnostics (host).
@@ -295,26 +312,29 @@ cbfs_status cbfs_autotune(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tun
 /* ------------------------------------------------------------------------ *
  * Landmark-labeling queries over cluster labels (Section 4.2; Algorithm
  * "Framework of Landmark Labeling", Query).  query(s, t) = min over clusters c
- * and sources x of c of d(x, s) + d(x, t); per cluster this is found from the
- * labels by the lowest non-empty intersection of the offset subsets of s and
- * t.  Only offsets -R..0 are needed: the center alone already gives offset
- * sum 0.  Requires one mask word per cluster (k <= 64).
+ * and sources x of c of d(x, s) + d(x, t); per cluster this is
+ * d(c,s) + d(c,t) plus the lowest offset sum a + b < 0 whose subsets
+ * intersect (M_a(s) & M_b(t) non-empty), else plus 0: the center alone gives
+ * offset sum 0.  A pair with a + b < 0 has both offsets <= R - 1, so the
+ * labels keep offsets -R .. R-1 (2R planes; none for R = 0).  Requires one
+ * mask word per cluster (k <= 64).
  *
  * cbfs_labels_pack: cluster-major C-BFS outputs (dist [C][n], masks
  * [C][2R+1][n][1], device) -> vertex-major labels dist_vm [n][C] and
- * mask_vm [n][C][R+1] (planes o = -R..0, device), so one query reads two
- * contiguous rows.
+ * mask_vm [n][C][2R] (planes o = -R .. R-1, device; may be NULL for R = 0),
+ * so one query reads two contiguous rows.
  *
  * cbfs_query_batch: ans[j] = query(s[j], t[j]) (device arrays of length q),
  * CBFS_UNREACHED when no cluster reaches both endpoints.  Vertex ids are not
  * range-checked on the device: out-of-range ids are the caller's error.
+ * Errors: CBFS_E_ARG (null pointers, sizes, R outside [0, 1024]); CBFS_E_HIP.
  * ------------------------------------------------------------------------ */
 typedef struct {
     int64_t n;               /* vertices                        */
     int32_t num_clusters;    /* C                               */
     int32_t radius;          /* R                               */
     const uint32_t *dist_vm; /* device [n][C]                   */
-    const uint64_t *mask_vm; /* device [n][C][R+1]              */
+    const uint64_t *mask_vm; /* device [n][C][2R]               */
 } cbfs_labels;
 
 cbfs_status cbfs_labels_pack(const uint32_t *dist, const uint64_t *masks, int32_t num_clusters,

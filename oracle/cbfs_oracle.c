@@ -20,7 +20,10 @@
  * distances.  A source farther than R from the center in offset at some
  * reachable vertex (or reaching a vertex the center does not reach) makes the
  * cluster's status CBFS_E_RADIUS; the Fact and Corollary of Section 3.1 bound
- * every offset by the source's distance to the center.
+ * every offset by the source's distance to the center.  Such a cluster's
+ * outputs are then defined as dist = UINT32_MAX and every mask word 0 (the
+ * problem statement takes the cluster's diameter as given; a cluster that
+ * breaks it gets no partial answer).
  *
  * Layouts (all row-major):
  *   row_ptr[n+1], col[m]            int32 CSR, rows = out-neighbours
@@ -265,6 +268,12 @@ int oracle_cbfs(int64_t n, const int32_t *row_ptr, const int32_t *col,
             if (ec.violated) violated = 1;
         }
         status[c] = violated ? OR_E_RADIUS : OR_OK;
+        if (violated) {
+            /* the boundary's definition of a violating cluster's outputs:
+             * unreachable everywhere, no source at any offset */
+            for (int64_t v = 0; v < n; v++) dc[v] = UINT32_MAX;
+            memset(mc, 0, sizeof(uint64_t) * (size_t)P * (size_t)n * (size_t)W);
+        }
     }
     free(d0);
     free(db);

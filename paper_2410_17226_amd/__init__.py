@@ -13,5 +13,5 @@ from ._binding import (  # noqa: F401
     build_csr, top_degree, select_clusters,
     Tuning, run_batch_workspace_size, run_batch, autotune,
     labels_pack, query_batch, status_string,
-    last_run_stats, profile_enable, profile_read, KERNEL_KINDS,
+    last_run_stats, profile_enable, profile_read, KERNEL_KINDS, release,
 )

@@ -1,6 +1,7 @@
 """ctypes binding of libcbfs.so (names follow ``include/cbfs.h``)."""
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -22,6 +23,7 @@ SYMBOLS = [
     "cbfs_select_clusters", "cbfs_run_batch_workspace_size", "cbfs_run_batch",
     "cbfs_last_run_stats", "cbfs_profile_enable", "cbfs_profile_read",
     "cbfs_labels_pack", "cbfs_query_batch", "cbfs_autotune_workspace_size", "cbfs_autotune",
+    "cbfs_release",
 ]
 KERNEL_KINDS = ["tiles", "init", "seed", "push", "pull", "finalize", "persistent", "labels", "query"]
 
@@ -134,8 +136,23 @@ def load():
     lib.cbfs_autotune_workspace_size.restype = sz
     lib.cbfs_autotune.argtypes = [P, P, P, i32, P, P, P, P, sz, P, P, P, i32, P]
     lib.cbfs_autotune.restype = i32
+    lib.cbfs_release.argtypes = []
+    lib.cbfs_release.restype = i32
     _lib = lib
+    # the library's pinned buffers and events go back while the HIP runtime is
+    # still up (this handler runs before torch's own exit handlers)
+    atexit.register(_release_at_exit)
     return lib
+
+
+def _release_at_exit():
+    if _lib is not None:
+        _lib.cbfs_release()
+
+
+def release():
+    """``cbfs_release``: free the library's pinned host buffers and events now."""
+    _check(load().cbfs_release(), "cbfs_release")
 
 
 def exported_symbols():
@@ -303,13 +320,14 @@ def autotune(row_ptr_d, col_d, cluster_ptr, sources, R: int, start: Tuning | Non
 
 
 def labels_pack(dist, masks, R: int, stream=None):
-    """``cbfs_labels_pack``: vertex-major labels (dist_vm int32[n][C], mask_vm int64[n][C][R+1])."""
+    """``cbfs_labels_pack``: vertex-major labels (dist_vm int32[n][C], mask_vm int64[n][C][2R],
+    planes -R .. R-1)."""
     torch = _torch()
     C, P, n, W = masks.shape
     if W != 1:
         raise ValueError("labels need one mask word per cluster")
     dist_vm = torch.empty((n, C), dtype=torch.int32, device=masks.device)
-    mask_vm = torch.empty((n, C, R + 1), dtype=torch.int64, device=masks.device)
+    mask_vm = torch.empty((n, C, 2 * R), dtype=torch.int64, device=masks.device)
     _check(load().cbfs_labels_pack(_dptr(dist), _dptr(masks), C, n, int(R), _dptr(dist_vm), _dptr(mask_vm),
                                    _stream_ptr(stream)), "cbfs_labels_pack")
     return dist_vm, mask_vm

@@ -53,6 +53,7 @@ static_assert(BLOCK * 4 <= STAGE_CAP, "one direct push pass fits the LDS stager"
 constexpr int MAX_W = 16;           // max words per vertex in a group
 constexpr uint32_t UNREACHED = 0xFFFFFFFFu;
 constexpr int32_t E_RADIUS = -5;
+constexpr int32_t E_HIP = -7;
 
 struct GraphArgs {
     int64_t n, m;

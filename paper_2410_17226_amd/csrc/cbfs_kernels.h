@@ -57,6 +57,11 @@ hipError_t launch_pull(int W, int WC, const SlotArgs &s, const GraphArgs &gr, co
 hipError_t launch_build_queue(const SlotArgs &s, const GraphArgs &gr, int32_t round, hipStream_t st);
 hipError_t launch_finalize(int W, int WC, const SlotArgs &s, int64_t n, const GroupDesc &g, const OutArgs &o,
                            hipStream_t st);
+// Status clean-up after a batch: every cluster whose status is not CBFS_OK
+// gets dist = CBFS_UNREACHED and zero masks; with *abort_flag != 0 (nullable)
+// every cluster first gets CBFS_E_HIP.
+hipError_t launch_scrub(const OutArgs &o, int64_t n, int32_t C, int32_t WC, const int32_t *abort_flag,
+                        hipStream_t st);
 // Blocks of the persistent kernel on the current device: per_cu per compute
 // unit (0 = as many as can be resident), capped at what can be resident.
 hipError_t persistent_grid(int W, int WC, int per_cu, int *blocks);

@@ -106,6 +106,27 @@ __global__ void k_finalize(SlotArgs s, int64_t n, GroupDesc g, OutArgs o)
                          (int64_t)gridDim.x * blockDim.x);
 }
 
+// The outputs of a cluster whose status is not CBFS_OK are defined as
+// dist = CBFS_UNREACHED and every mask word 0 (its search was cut short or
+// its radius did not hold, so no partial result is handed back).  With
+// abort_flag set (the persistent kernel stopped early), every cluster of the
+// batch gets CBFS_E_HIP first.  Grid (x, C): blocks of cluster blockIdx.y
+// stride over its dist row and its 2R+1 contiguous mask planes.
+__global__ __launch_bounds__(BLOCK) void k_scrub(OutArgs o, int64_t n, int32_t WC, const int32_t *abort_flag)
+{
+    const int32_t c = blockIdx.y;
+    const bool aborted = abort_flag && *abort_flag != 0;
+    if (!aborted && o.status[c] == 0) return;  // block-uniform
+    __syncthreads();  // every thread has read the status before it is overwritten
+    if (aborted && blockIdx.x == 0 && threadIdx.x == 0) o.status[c] = E_HIP;
+    const int64_t tid = (int64_t)blockIdx.x * BLOCK + threadIdx.x, stride = (int64_t)gridDim.x * BLOCK;
+    uint32_t *d = o.dist + (size_t)c * (size_t)n;
+    for (int64_t v = tid; v < n; v += stride) d[v] = UNREACHED;
+    const int64_t words = (2 * (int64_t)o.R + 1) * n * WC;
+    uint64_t *m = o.masks + (size_t)c * (size_t)words;
+    for (int64_t k = tid; k < words; k += stride) m[k] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // Persistent batch kernel.
 // ---------------------------------------------------------------------------
@@ -516,6 +537,15 @@ hipError_t launch_finalize(int W, int WC, const SlotArgs &s, int64_t n, const Gr
 {
     int blocks = (int)std::min<int64_t>(8192, (n + BLOCK - 1) / BLOCK);
     CBFS_DISPATCH(W, WC, (k_finalize<W, WC><<<blocks, BLOCK, 0, st>>>(s, n, g, o)));
+    return hipGetLastError();
+}
+
+hipError_t launch_scrub(const OutArgs &o, int64_t n, int32_t C, int32_t WC, const int32_t *abort_flag,
+                        hipStream_t st)
+{
+    const int64_t per = (n + BLOCK * 64 - 1) / (BLOCK * 64);  // about 64 vertices per thread
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(per, 32));
+    k_scrub<<<dim3(nb, (unsigned)C), BLOCK, 0, st>>>(o, n, WC, abort_flag);
     return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -294,14 +295,87 @@ static GraphArgs graph_args(const Plan &p, const cbfs_csr *g, char *ws)
     return gr;
 }
 
-// Pinned host words the level loop reads the frontier counters into.
+// ---------------------------------------------------------------------------
+// Host resources the library owns: pinned staging buffers for the batch
+// tables (a ring, each buffer reused once the event recorded after its upload
+// has completed, so a call never waits for the device unless every buffer is
+// still in flight), and pinned words the host loop reads the frontier
+// counters into.  All of it is released by cbfs_release().
+// ---------------------------------------------------------------------------
+namespace {
+struct StageBuf {
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;  // recorded after the upload that last used the buffer
+    bool pending = false;
+};
+constexpr int STAGE_RING = 8;
+std::mutex g_res_mu;
+std::vector<StageBuf> g_stage;                 // at most STAGE_RING
+int g_stage_next = 0;
+std::vector<unsigned long long *> g_counters;  // one pinned block per host thread that ran a host loop
+unsigned g_res_gen = 1;                        // bumped by cbfs_release; thread caches compare it
+}  // namespace
+
+// Copies `bytes` of host memory into a pinned staging buffer and enqueues its
+// upload to `dst` on `st`; the buffer is reused only after the upload has run.
+static cbfs_status staged_upload(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lock(g_res_mu);
+    hipError_t e;
+    StageBuf *b = nullptr;
+    for (auto &x : g_stage)  // a free buffer that fits
+        if (x.cap >= bytes && (!x.pending || hipEventQuery(x.done) == hipSuccess)) {
+            b = &x;
+            break;
+        }
+    if (!b && (int)g_stage.size() < STAGE_RING) {
+        g_stage.reserve(STAGE_RING);
+        g_stage.push_back(StageBuf{});
+        b = &g_stage.back();
+        if ((e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)) != hipSuccess) {
+            g_stage.pop_back();
+            return hip_fail("staging event", e);
+        }
+    }
+    if (!b) {  // every buffer in flight: take the next one in turn once its upload ran
+        b = &g_stage[g_stage_next];
+        g_stage_next = (g_stage_next + 1) % STAGE_RING;
+        if ((e = hipEventSynchronize(b->done)) != hipSuccess) return hip_fail("staging wait", e);
+    }
+    if (b->pending && (e = hipEventSynchronize(b->done)) != hipSuccess) return hip_fail("staging wait", e);
+    b->pending = false;
+    if (b->cap < bytes) {
+        if (b->host && (e = hipHostFree(b->host)) != hipSuccess) return hip_fail("staging free", e);
+        b->host = nullptr;
+        b->cap = 0;
+        size_t cap = 4096;
+        while (cap < bytes) cap *= 2;
+        if ((e = hipHostMalloc(&b->host, cap, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail("staging allocation", e);
+        b->cap = cap;
+    }
+    std::memcpy(b->host, src, bytes);
+    if ((e = hipMemcpyAsync(dst, b->host, bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_fail("batch upload", e);
+    if ((e = hipEventRecord(b->done, st)) != hipSuccess) return hip_fail("staging event record", e);
+    b->pending = true;
+    return CBFS_OK;
+}
+
+// Pinned host words the level loop reads the frontier counters into (one
+// block per host thread, allocated on its first host-loop call).
 static unsigned long long *pinned_counters()
 {
     thread_local unsigned long long *buf = nullptr;
-    if (!buf) {
+    thread_local unsigned gen = 0;
+    std::lock_guard<std::mutex> lock(g_res_mu);
+    if (!buf || gen != g_res_gen) {
         void *p = nullptr;
         if (hipHostMalloc(&p, 64, hipHostMallocDefault) != hipSuccess) return nullptr;
         buf = (unsigned long long *)p;
+        gen = g_res_gen;
+        g_counters.push_back(buf);
     }
     return buf;
 }
@@ -479,7 +553,8 @@ extern "C" cbfs_status cbfs_run_batch(const cbfs_csr *g, const cbfs_batch *b, co
     g_last.host.slots = p.slots;
     g_last.host.mode = p.mode;
 
-    // one upload of the batch tables, then the host arrays are released
+    // one upload of the batch tables through a pinned staging buffer (no wait
+    // for earlier work on the stream); the host arrays are not used afterwards
     std::vector<char> stage(p.off_slots, 0);
     std::memcpy(stage.data() + p.off_cptr, b->cluster_ptr, sizeof(int32_t) * (size_t)(p.C + 1));
     std::memcpy(stage.data() + p.off_src, b->sources, sizeof(int32_t) * (size_t)p.total_sources);
@@ -493,15 +568,48 @@ extern "C" cbfs_status cbfs_run_batch(const cbfs_csr *g, const cbfs_batch *b, co
     }
     hipError_t e;
     const size_t lo = p.off_cptr, hi = p.off_ctl;
-    if ((e = hipMemcpyAsync(ws + lo, stage.data() + lo, hi - lo, hipMemcpyHostToDevice, st)) != hipSuccess)
-        return hip_fail("batch upload", e);
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail("upload sync", e);
+    if ((rc = staged_upload(ws + lo, stage.data() + lo, hi - lo, st)) != CBFS_OK) return rc;
     if ((e = PROF(CBFS_KERNEL_TILES, st,
                   launch_tiles(g->row_ptr, p.n, p.m, p.ntiles, (int32_t *)(ws + p.off_tiles_row),
                                (int32_t *)(ws + p.off_tiles_edge), st))) != hipSuccess)
         return hip_fail("tiles", e);
-    if (p.mode == CBFS_MODE_HOST_LOOP) return run_host_loop(p, g, b, dist, masks, cluster_status, ws, st);
-    return run_persistent(p, g, dist, masks, cluster_status, ws, st);
+    const int32_t *abort_flag = nullptr;
+    if (p.mode == CBFS_MODE_HOST_LOOP) {
+        rc = run_host_loop(p, g, b, dist, masks, cluster_status, ws, st);
+    } else {
+        rc = run_persistent(p, g, dist, masks, cluster_status, ws, st);
+        abort_flag = (const int32_t *)(ws + p.off_ctl + sizeof(unsigned int) * CTL_WORDS);
+    }
+    if (rc != CBFS_OK) return rc;
+    // clusters whose status is not CBFS_OK: defined outputs (UNREACHED, zero masks)
+    const OutArgs o{dist, masks, cluster_status, p.R};
+    if ((e = PROF(CBFS_KERNEL_FINALIZE, st, launch_scrub(o, p.n, p.C, p.WC, abort_flag, st))) != hipSuccess)
+        return hip_fail("status scrub", e);
+    return CBFS_OK;
+}
+
+extern "C" cbfs_status cbfs_release(void)
+{
+    std::lock_guard<std::mutex> lock(g_res_mu);
+    cbfs_status rc = CBFS_OK;
+    for (auto &b : g_stage) {
+        if (b.pending && hipEventSynchronize(b.done) != hipSuccess) rc = CBFS_E_HIP;
+        if (b.done && hipEventDestroy(b.done) != hipSuccess) rc = CBFS_E_HIP;
+        if (b.host && hipHostFree(b.host) != hipSuccess) rc = CBFS_E_HIP;
+    }
+    g_stage.clear();
+    g_stage_next = 0;
+    for (auto *c : g_counters)
+        if (hipHostFree(c) != hipSuccess) rc = CBFS_E_HIP;
+    g_counters.clear();
+    g_res_gen++;
+    for (auto &r : g_prof) {
+        hipEventDestroy(r.start);
+        hipEventDestroy(r.stop);
+    }
+    g_prof.clear();
+    g_prof_on = false;
+    return rc == CBFS_OK ? CBFS_OK : fail(rc, "cbfs_release: a HIP call failed");
 }
 
 extern "C" cbfs_status cbfs_last_run_stats(cbfs_run_stats *out)

@@ -50,15 +50,20 @@ def gpu_cbfs(rp, col, cp, src, R, tuning=None):
 
 
 def assert_same(gpu, ref, where=""):
+    """Every output word equal, violating clusters included (their outputs are
+    defined: dist UNREACHED and zero masks at every vertex)."""
     gd, gm, gs = gpu
     od, om, os_ = ref
     assert np.array_equal(gs, os_), f"{where} status {gs} vs {os_}"
-    ok = os_ == 0
-    assert np.array_equal(gd[ok], od[ok]), f"{where} dist mismatch in clusters {np.nonzero(ok)[0]}"
-    for c in np.nonzero(ok)[0]:
+    for c in range(os_.size):
+        if not np.array_equal(gd[c], od[c]):
+            bad = np.nonzero(gd[c] != od[c])[0]
+            raise AssertionError(f"{where} dist of cluster {c} (status {os_[c]}) differs at {bad[:5].tolist()}")
         if not np.array_equal(gm[c], om[c]):
             bad = np.argwhere(gm[c] != om[c])
-            raise AssertionError(f"{where} masks of cluster {c} differ at {bad[:5].tolist()}")
+            raise AssertionError(f"{where} masks of cluster {c} (status {os_[c]}) differ at {bad[:5].tolist()}")
+    bad_c = np.nonzero(os_ != 0)[0]
+    assert (gd[bad_c] == 0xFFFFFFFF).all() and not gm[bad_c].any(), f"{where} violating outputs not cleared"
 
 
 TUNINGS = [None, dict(alpha=-1.0), dict(force_pull=1), dict(group_words=1), dict(group_words=8, alpha=5.0),

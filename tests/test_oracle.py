@@ -243,6 +243,21 @@ def test_radius_violation_and_unreachable():
     assert st[0] == oracle.E_RADIUS
 
 
+def test_violating_cluster_outputs_are_cleared():
+    """A cluster whose radius does not hold returns dist = UINT32_MAX and zero
+    masks at every vertex; clusters beside it in the same call are unaffected
+    (each equals its own single-cluster call)."""
+    rp, col = csr_of(6, [(0, 1), (1, 2), (2, 3), (4, 5)])
+    cp, src = [0, 2, 4, 6], [1, 3, 1, 0, 2, 1]
+    dist, masks, st = oracle.cbfs(rp, col, cp, src, R=1)
+    assert list(st) == [oracle.E_RADIUS, 0, 0]
+    assert (dist[0] == U32MAX).all() and not masks[0].any()
+    for c in (1, 2):
+        d1, m1, s1 = oracle.cbfs(rp, col, [0, 2], src[cp[c]:cp[c + 1]], R=1)
+        assert s1[0] == 0 and np.array_equal(dist[c], d1[0]) and np.array_equal(masks[c], m1[0])
+    assert dist[1, 1] == 0 and dist[1, 3] == 2   # the valid cluster keeps its distances
+
+
 def read_fixture(golden_dir):
     fx = {"vertex": [], "query": []}
     with open(os.path.join(golden_dir, "hand_example.txt")) as f:
@@ -383,6 +398,69 @@ def test_certificate_words_agrees_on_wide_disconnected_and_radius2():
     bm[0, v, 0] |= np.uint64(1)
     bd[v] += 1
     assert oracle.certificate_words(rp, col, cl, 1, bd, bm) > 0
+
+
+def _plant_cases(cl, dist, masks, R):
+    """Planted mistakes in words >= 1 of a multi-word cluster output, each one a
+    copy of (dist, masks) with exactly one defect:
+      - a bit of source 70 (word 1) moved to the neighbouring plane at a vertex;
+      - the same for source 200 (word 3), when the cluster has that many sources;
+      - source 130 (word 2) dropped at one vertex, and at every vertex;
+      - a source >= 64 moved from its own offset to offset 0 at its own vertex
+        (its distance to itself would read d(c, s) instead of 0)."""
+    k = cl.size
+    P = 2 * R + 1
+    reach = np.nonzero((dist != U32MAX) & (dist >= 2))[0]
+    v = int(reach[len(reach) // 2])
+    out = []
+
+    def moved(i, vv):
+        bad = masks.copy()
+        w, b = i // 64, np.uint64(1 << (i % 64))
+        p = [pl for pl in range(P) if bad[pl, vv, w] & b][0]
+        q = p + 1 if p + 1 < P else p - 1
+        bad[p, vv, w] ^= b
+        bad[q, vv, w] ^= b
+        return bad
+
+    out.append(("move70", dist, moved(70, v)))
+    if k > 200:
+        out.append(("move200", dist, moved(200, v)))
+    drop = masks.copy()
+    drop[:, v + 1 if dist[v + 1] != U32MAX else v, 130 // 64] &= ~np.uint64(1 << (130 % 64))
+    out.append(("drop130", dist, drop))
+    gone = masks.copy()                         # source 130 missing at every vertex
+    gone[:, :, 130 // 64] &= ~np.uint64(1 << (130 % 64))
+    out.append(("gone130", dist, gone))
+    i = k - 1                                   # a source in the last word
+    sv = int(cl[i])
+    own = masks.copy()
+    w, b = i // 64, np.uint64(1 << (i % 64))
+    p = [pl for pl in range(P) if own[pl, sv, w] & b][0]
+    assert p != R                               # d(c, s_i) >= 1
+    own[p, sv, w] ^= b
+    own[R, sv, w] |= b
+    out.append(("own_offset0", dist, own))
+    return out
+
+
+@pytest.mark.parametrize("k", [150, 256])
+def test_certificates_reject_mistakes_in_upper_words(k):
+    """Both certificate forms accept exact multi-word outputs (W = 3 and 4) and
+    reject a single planted mistake in a word >= 1 (a moved bit, a dropped
+    source, a source shifted off its own vertex's level 0)."""
+    n, s, d = synth.rmat_edges(11, 16, seed=7)
+    rp, col, _ = oracle.clean_csr(n, s, d)
+    c = int(oracle.top_degree(rp, 1)[0])
+    cl = oracle.cluster_around(rp, col, c, k, 1)
+    assert cl.size == k
+    dist, masks, st = oracle.cbfs(rp, col, [0, k], cl, R=1)
+    assert st[0] == 0 and masks.shape[-1] == (k + 63) // 64
+    for cert in (oracle.certificate, oracle.certificate_words):
+        assert cert(rp, col, cl, 1, dist[0], masks[0]) == 0
+    for name, bd, bm in _plant_cases(cl, dist[0], masks[0], 1):
+        for cert in (oracle.certificate, oracle.certificate_words):
+            assert cert(rp, col, cl, 1, bd, bm) > 0, f"{cert.__name__} accepted {name} (k={k})"
 
 
 def test_cleanup_c_matches_numpy_and_scipy():
