@@ -94,7 +94,23 @@ def main():
                     help="autotune the launch knobs on the first 16 clusters before timing (untimed)")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run one device-to-device copy of this many bytes (counter calibration)")
+    ap.add_argument("--gather-only", type=int, default=0,
+                    help="only run one gather of this many random 64-byte rows out of a 4 GiB table "
+                         "(counter calibration for scattered 64-byte reads)")
     args = ap.parse_args()
+    if args.gather_only:
+        import torch
+        rows = 1 << 26  # 4 GiB of 64-byte rows: far beyond every cache
+        table = torch.ones((rows, 8), dtype=torch.int64, device="cuda")
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7)
+        idx = torch.randint(0, rows, (args.gather_only,), device="cuda", generator=g)
+        torch.cuda.synchronize()
+        out = table.index_select(0, idx)
+        torch.cuda.synchronize()
+        print(json.dumps({"gather_rows": args.gather_only, "row_bytes": 64, "index_bytes": 8,
+                          "distinct_rows": int(torch.unique(idx).numel()), "check": int(out[:, 0].sum())}))
+        return
     if args.copy_only:
         import torch
         x = torch.empty(args.copy_only, dtype=torch.uint8, device="cuda")

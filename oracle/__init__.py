@@ -10,6 +10,8 @@ product package, and the product package never imports it.
 * ``bfs``             -- single-source BFS (Appendix A, sequential form).
 * ``query_landmarks`` -- brute-force landmark-labeling query (Section 4.2,
                          Algorithm "Framework of Landmark Labeling", Query).
+* ``pair_distances``  -- exact delta(s, t) per pair (one BFS from s), the
+                         ground truth landmark answers bound from above.
 * ``query_labels``    -- the same query from encoded labels by the lowest
                          non-empty intersection (Section 4.2).
 * ``certificate``     -- BFS-distance certificate of any encoded output.
@@ -62,6 +64,8 @@ def _load():
         lib.oracle_cbfs.restype = ctypes.c_int
         lib.oracle_query_landmarks.argtypes = [i64, P, P, i32, P, P, i64, P, P, P, i32]
         lib.oracle_query_landmarks.restype = ctypes.c_int
+        lib.oracle_pair_distances.argtypes = [i64, P, P, i64, P, P, P, i32]
+        lib.oracle_pair_distances.restype = ctypes.c_int
         lib.oracle_query_labels.argtypes = [i64, i32, i32, P, P, i64, P, P, P]
         lib.oracle_query_labels.restype = ctypes.c_int
         lib.oracle_certificate.argtypes = [i64, P, P, i32, P, i32, i32, P, P, i32]
@@ -142,6 +146,19 @@ def query_landmarks(row_ptr, col, cluster_ptr, sources, qs, qt, nthreads: int = 
     if rc != 0:
         raise ValueError(f"oracle_query_landmarks failed: {rc}")
     return ans
+
+
+def pair_distances(row_ptr, col, qs, qt, nthreads: int = 0) -> np.ndarray:
+    """Exact delta(s, t) per pair, one plain BFS from each s (uint32, UINT32_MAX = unreachable)."""
+    row_ptr, col, n = _csr(row_ptr, col)
+    qs = np.ascontiguousarray(qs, dtype=np.int32)
+    qt = np.ascontiguousarray(qt, dtype=np.int32)
+    out = np.empty(qs.size, dtype=np.uint32)
+    rc = _load().oracle_pair_distances(n, _p(row_ptr), _p(col), qs.size, _p(qs), _p(qt), _p(out),
+                                       int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_pair_distances failed: {rc}")
+    return out
 
 
 def query_labels(dist, masks, qs, qt) -> np.ndarray:

@@ -332,6 +332,46 @@ int oracle_query_landmarks(int64_t n, const int32_t *row_ptr, const int32_t *col
     return rc;
 }
 
+/* Exact hop distance of each pair: out[j] = delta(qs[j], qt[j]) from one
+ * plain FIFO BFS rooted at qs[j] (UINT32_MAX when qt[j] is unreachable).
+ * The ground truth a landmark answer is bounded by from below (Section 4.2:
+ * a landmark x gives delta(x,s) + delta(x,t) >= delta(s,t), the triangle
+ * inequality).  Parallel over pairs, one BFS buffer pair per thread. */
+typedef struct {
+    int64_t n;
+    const int32_t *row_ptr, *col, *qs, *qt;
+    uint32_t *out;
+    int32_t *bufs;
+} pair_ctx;
+
+static void pair_body(int64_t lo, int64_t hi, int tid, void *p)
+{
+    pair_ctx *c = (pair_ctx *)p;
+    int32_t *d = c->bufs + (size_t)tid * 2 * (size_t)c->n;
+    int32_t *queue = d + c->n;
+    for (int64_t j = lo; j < hi; j++) {
+        bfs(c->n, c->row_ptr, c->col, c->qs[j], d, queue);
+        const int32_t x = d[c->qt[j]];
+        c->out[j] = x == UNREACHED ? UINT32_MAX : (uint32_t)x;
+    }
+}
+
+int oracle_pair_distances(int64_t n, const int32_t *row_ptr, const int32_t *col, int64_t q,
+                          const int32_t *qs, const int32_t *qt, uint32_t *out, int32_t nthreads)
+{
+    if (n <= 0 || q < 0) return OR_E_ARG;
+    for (int64_t j = 0; j < q; j++)
+        if (qs[j] < 0 || qs[j] >= n || qt[j] < 0 || qt[j] >= n) return OR_E_ARG;
+    int nt = nthreads_or_default(nthreads);
+    if (nt > q) nt = q > 0 ? (int)q : 1;
+    int32_t *bufs = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)n * (size_t)nt);
+    if (!bufs) return OR_E_NOMEM;
+    pair_ctx c = {n, row_ptr, col, qs, qt, out, bufs};
+    parallel_for(q, 1, nt, pair_body, &c);
+    free(bufs);
+    return OR_OK;
+}
+
 /* The same query from encoded labels (dist[C][n], masks[C][2R+1][n][1], k <= 64):
  * per cluster, scan offset pairs (a, b) in increasing order of a + b and stop at
  * the first non-empty intersection mask[a][s] & mask[b][t]; the candidate is

@@ -146,6 +146,50 @@ def test_rmat22_queries_sampled(rmat22):
     _log(f"bound holds on 64 pairs (mean slack {float(np.mean(ans.astype(np.int64) - exact)):.3f})")
 
 
+def _golden_pairs(golden_dir):
+    """The oracle's stored landmark answers and exact distances for the
+    serving labels (tests/golden/make_fullsize_golden.py serve_rmat22)."""
+    meta, rows = {}, []
+    with open(os.path.join(golden_dir, "serve_rmat22_pairs.txt")) as f:
+        for ln in f:
+            if ln.startswith("# n="):
+                meta = dict(kv.split("=") for kv in ln[2:].split())
+            elif not ln.startswith("#"):
+                rows.append(ln.split())
+    kind = np.array([r[0] for r in rows])
+    vals = np.array([[int(x) for x in r[1:]] for r in rows], dtype=np.int64)
+    return meta, kind, vals
+
+
+def test_rmat22_serving_labels_match_oracle_answers(rmat22, golden_dir):
+    """The 128-cluster serving labels answer 1,032 stored pairs (the first 1,000
+    of the benchmark's query stream, 24 with a landmark endpoint, 8 with s = t)
+    exactly as the oracle's brute-force landmark query does, and never below
+    the true distance (Section 4.2: one-sided error)."""
+    import hashlib
+    torch = _torch()
+    import paper_2410_17226_amd as P
+    cfg, rp, col, cp, src, dist, masks, st = rmat22
+    meta, kind, vals = _golden_pairs(golden_dir)
+    assert int(meta["n"]) == rp.size - 1 and int(meta["m"]) == col.size
+    assert meta["row_ptr_sha256"] == hashlib.sha256(rp.tobytes()).hexdigest()
+    assert meta["col_sha256"] == hashlib.sha256(col.tobytes()).hexdigest()
+    R = cfg["R"]
+    CQ = 128
+    qs = np.ascontiguousarray(vals[:, 0], dtype=np.int32)
+    qt = np.ascontiguousarray(vals[:, 1], dtype=np.int32)
+    dvm, mvm = P.labels_pack(dist[:CQ], masks[:CQ], R)
+    got = P.query_batch(dvm, mvm, R, torch.from_numpy(qs).cuda(), torch.from_numpy(qt).cuda())
+    got = got.cpu().numpy().view(np.uint32).astype(np.int64)
+    del dvm, mvm
+    assert np.array_equal(got, vals[:, 2]), f"{int((got != vals[:, 2]).sum())} answers differ"
+    assert (got >= vals[:, 3]).all()
+    lm = kind == "landmark_s"
+    assert np.array_equal(got[lm], vals[lm, 3])
+    _log(f"serving labels: {got.size} answers identical to the oracle's; "
+         f"{int((got == vals[:, 3]).sum())} exact, mean slack {float(np.mean(got - vals[:, 3])):.3f}")
+
+
 def test_grid4096_batch_sampled_parity():
     _torch()
     cfg, rp, col, cp, src = _inputs("grid4096")

@@ -339,6 +339,31 @@ def test_query_oracles_agree_and_bound(seed):
         assert a[j] == 2 * min(D[x, qs[j]] for x in src)
 
 
+@pytest.mark.parametrize("name,g", small_graphs())
+def test_pair_distances_match_library_shortest_paths(name, g):
+    """Exact pair distances (the ground truth of the landmark bound) against
+    scipy's all-pairs shortest paths, unreachable pairs included."""
+    n, s, d = g
+    rp, col, _ = oracle.clean_csr(n, s, d, flags=7)
+    D = apsp(rp, col)
+    nv = rp.size - 1
+    qs, qt = synth.query_pairs(nv, 500, 3)
+    qs[:5] = qt[:5]  # s == t
+    got = oracle.pair_distances(rp, col, qs, qt, nthreads=3)
+    want = D[qs, qt]
+    assert np.array_equal(got[want >= 0].astype(np.int64), want[want >= 0])
+    assert (got[want < 0] == U32MAX).all()
+    assert (got[:5] == 0).all()
+
+
+def test_pair_distances_path_closed_form():
+    n = 30
+    rp, col = csr_of(n, [(i, i + 1) for i in range(n - 1)])
+    qs, qt = np.meshgrid(np.arange(n, dtype=np.int32), np.arange(n, dtype=np.int32))
+    got = oracle.pair_distances(rp, col, qs.ravel(), qt.ravel())
+    assert np.array_equal(got.astype(np.int64), np.abs(qs.ravel() - qt.ravel()).astype(np.int64))
+
+
 def test_query_labels_radius2_matches_bruteforce():
     n, s, d = synth.grid_edges(20, 0.1, seed=9)
     rp, col, _ = oracle.clean_csr(n, s, d)
