@@ -20,8 +20,10 @@
  *   - "device" pointers are HIP device memory of the current device; "host"
  *     pointers are ordinary process memory.  The library never allocates
  *     device memory: every device buffer, including the workspace, belongs to
- *     the caller.  Host arrays are read (and host outputs written) before the
- *     call returns.
+ *     the caller (the one exception is the fixed scratch array that
+ *     cbfs_run_batch_static uses in place of a workspace, part of the
+ *     library's code object).  Host arrays are read (and host outputs
+ *     written) before the call returns.
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).
  *   - Every entry point returns a cbfs_status.  Argument errors are detected on
  *     the host before anything is enqueued; such a call writes no output.
@@ -212,6 +214,32 @@ size_t cbfs_run_batch_workspace_size(const cbfs_csr *g, const cbfs_batch *b, con
 cbfs_status cbfs_run_batch(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *t,
                            uint32_t *dist, uint64_t *masks, int32_t *cluster_status,
                            void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ *
+ * cbfs_run_batch without any allocation, for callers that cannot allocate
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, outputs, statuses and kernels as
+ * cbfs_run_batch, except that the workspace is the library's own device array
+ * of CBFS_STATIC_SCRATCH_BYTES bytes (one per device, created when the library's
+ * code is loaded on that device and held until the process ends).  The call
+ * makes no device or pinned host allocation of any kind.
+ *   - The current device must be the one that owns the stream and the
+ *     buffers; the array's device address is looked up on the first call on
+ *     each device.
+ *   - The batch tables go up from pageable host memory, so the call waits
+ *     for the stream once (after that upload).  CBFS_MODE_HOST_LOOP also
+ *     waits once per round, as in cbfs_run_batch.
+ *   - Every call on one device shares that device's array, which keeps the
+ *     last call's contents (the search clears what it needs): calls that
+ *     overlap on one device (other threads, other streams) race and give
+ *     undefined outputs.  Serialise them.
+ * Errors: those of cbfs_run_batch; CBFS_E_WORKSPACE (before any launch) when
+ * cbfs_run_batch_workspace_size for these arguments exceeds
+ * CBFS_STATIC_SCRATCH_BYTES.
+ * ------------------------------------------------------------------------ */
+#define CBFS_STATIC_SCRATCH_BYTES (64u << 20)
+cbfs_status cbfs_run_batch_static(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *t,
+                                  uint32_t *dist, uint64_t *masks, int32_t *cluster_status, void *stream);
 
 /* Releases the host resources the library holds (the pinned staging buffers
  * and their events, the pinned counter words of the host loop, the calling

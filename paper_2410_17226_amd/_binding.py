@@ -23,7 +23,7 @@ SYMBOLS = [
     "cbfs_select_clusters", "cbfs_run_batch_workspace_size", "cbfs_run_batch",
     "cbfs_last_run_stats", "cbfs_profile_enable", "cbfs_profile_read",
     "cbfs_labels_pack", "cbfs_query_batch", "cbfs_autotune_workspace_size", "cbfs_autotune",
-    "cbfs_release",
+    "cbfs_release", "cbfs_run_batch_static",
 ]
 KERNEL_KINDS = ["tiles", "init", "seed", "push", "pull", "finalize", "persistent", "labels", "query"]
 
@@ -136,6 +136,8 @@ def load():
     lib.cbfs_autotune_workspace_size.restype = sz
     lib.cbfs_autotune.argtypes = [P, P, P, i32, P, P, P, P, sz, P, P, P, i32, P]
     lib.cbfs_autotune.restype = i32
+    lib.cbfs_run_batch_static.argtypes = [P, P, P, P, P, P, P]
+    lib.cbfs_run_batch_static.restype = i32
     lib.cbfs_release.argtypes = []
     lib.cbfs_release.restype = i32
     _lib = lib
@@ -288,6 +290,32 @@ def run_batch(row_ptr_d, col_d, cluster_ptr, sources, R: int, tuning: Tuning | N
                             _dptr(dist), _dptr(masks), _dptr(status), _dptr(workspace),
                             workspace.numel(), _stream_ptr(stream))
     _check(rc, "cbfs_run_batch")
+    return dist, masks, status
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def run_batch_static(row_ptr_d, col_d, cluster_ptr, sources, R: int, tuning: Tuning | None = None,
+                     out=None, stream=None):
+    """``cbfs_run_batch_static``: ``run_batch`` with the library's own device
+    scratch array as the workspace (no allocation by the library).  ``out``
+    may pass preallocated output tensors; otherwise they are created here."""
+    torch = _torch()
+    lib = load()
+    g, b, t, cptr, srcs = _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, tuning)
+    C = cptr.size - 1
+    n = row_ptr_d.numel() - 1
+    if out is None:
+        W = words_for(cptr)
+        dev = row_ptr_d.device
+        out = (torch.empty((C, n), dtype=torch.int32, device=dev),
+               torch.empty((C, 2 * R + 1, n, W), dtype=torch.int64, device=dev),
+               torch.empty(C, dtype=torch.int32, device=dev))
+    dist, masks, status = out
+    rc = lib.cbfs_run_batch_static(ctypes.byref(g), ctypes.byref(b), ctypes.byref(t) if t is not None else None,
+                                   _dptr(dist), _dptr(masks), _dptr(status), _stream_ptr(stream))
+    _check(rc, "cbfs_run_batch_static")
     return dist, masks, status
 
 

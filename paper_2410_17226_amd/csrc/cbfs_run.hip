@@ -389,15 +389,16 @@ static unsigned long long *pinned_counters()
         return e__;                   \
     }()
 
+// hc: host words the frontier counters are read into each round (pinned
+// words of the library, or caller memory in the no-allocation form)
 static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_batch *b, uint32_t *dist,
-                                 uint64_t *masks, int32_t *status, char *ws, hipStream_t st)
+                                 uint64_t *masks, int32_t *status, char *ws, hipStream_t st,
+                                 unsigned long long *hc)
 {
     const GraphArgs gr = graph_args(p, g, ws);
     const int32_t *d_cptr = (const int32_t *)(ws + p.off_cptr);
     const int32_t *d_src = (const int32_t *)(ws + p.off_src);
     OutArgs o{dist, masks, status, p.R};
-    unsigned long long *hc = pinned_counters();
-    if (!hc) return fail(CBFS_E_NOMEM, "cbfs_run_batch: pinned host counters");
     hipError_t e;
     cbfs_run_stats &rs = g_last.host;
     const SlotArgs s = slot_at(p, ws, 0);
@@ -532,19 +533,14 @@ extern "C" size_t cbfs_run_batch_workspace_size(const cbfs_csr *g, const cbfs_ba
     return p.total;
 }
 
-extern "C" cbfs_status cbfs_run_batch(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *t,
-                                      uint32_t *dist, uint64_t *masks, int32_t *cluster_status,
-                                      void *workspace, size_t workspace_bytes, void *stream)
+// The batch on a planned, checked workspace.  no_alloc: take no pinned host
+// memory (the tables go up from pageable memory followed by one stream wait;
+// the host loop reads its counters into a local array).
+static cbfs_status run_batch_planned(const Plan &p, const cbfs_csr *g, const cbfs_batch *b, uint32_t *dist,
+                                     uint64_t *masks, int32_t *cluster_status, char *ws, hipStream_t st,
+                                     bool no_alloc)
 {
-    g_last_error.clear();
-    Plan p;
-    cbfs_status rc = make_plan(g, b, t, p, true);
-    if (rc != CBFS_OK) return rc;
-    if (!dist || !masks || !cluster_status || !workspace)
-        return fail(CBFS_E_ARG, "cbfs_run_batch: null output or workspace");
-    if (workspace_bytes < p.total) return fail(CBFS_E_WORKSPACE, "cbfs_run_batch: workspace too small");
-    hipStream_t st = (hipStream_t)stream;
-    char *ws = (char *)workspace;
+    cbfs_status rc;
     g_last = LastRun{};
     g_last.valid = true;
     g_last.stream = st;
@@ -568,14 +564,24 @@ extern "C" cbfs_status cbfs_run_batch(const cbfs_csr *g, const cbfs_batch *b, co
     }
     hipError_t e;
     const size_t lo = p.off_cptr, hi = p.off_ctl;
-    if ((rc = staged_upload(ws + lo, stage.data() + lo, hi - lo, st)) != CBFS_OK) return rc;
+    if (!no_alloc) {
+        if ((rc = staged_upload(ws + lo, stage.data() + lo, hi - lo, st)) != CBFS_OK) return rc;
+    } else {
+        // pageable source: wait for the copy before `stage` goes away
+        if ((e = hipMemcpyAsync(ws + lo, stage.data() + lo, hi - lo, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return hip_fail("batch upload", e);
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail("batch upload wait", e);
+    }
     if ((e = PROF(CBFS_KERNEL_TILES, st,
                   launch_tiles(g->row_ptr, p.n, p.m, p.ntiles, (int32_t *)(ws + p.off_tiles_row),
                                (int32_t *)(ws + p.off_tiles_edge), st))) != hipSuccess)
         return hip_fail("tiles", e);
     const int32_t *abort_flag = nullptr;
     if (p.mode == CBFS_MODE_HOST_LOOP) {
-        rc = run_host_loop(p, g, b, dist, masks, cluster_status, ws, st);
+        unsigned long long local[4] = {0, 0, 0, 0};
+        unsigned long long *hc = no_alloc ? local : pinned_counters();
+        if (!hc) return fail(CBFS_E_NOMEM, "cbfs_run_batch: pinned host counters");
+        rc = run_host_loop(p, g, b, dist, masks, cluster_status, ws, st, hc);
     } else {
         rc = run_persistent(p, g, dist, masks, cluster_status, ws, st);
         abort_flag = (const int32_t *)(ws + p.off_ctl + sizeof(unsigned int) * CTL_WORDS);
@@ -586,6 +592,68 @@ extern "C" cbfs_status cbfs_run_batch(const cbfs_csr *g, const cbfs_batch *b, co
     if ((e = PROF(CBFS_KERNEL_FINALIZE, st, launch_scrub(o, p.n, p.C, p.WC, abort_flag, st))) != hipSuccess)
         return hip_fail("status scrub", e);
     return CBFS_OK;
+}
+
+extern "C" cbfs_status cbfs_run_batch(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *t,
+                                      uint32_t *dist, uint64_t *masks, int32_t *cluster_status,
+                                      void *workspace, size_t workspace_bytes, void *stream)
+{
+    g_last_error.clear();
+    Plan p;
+    cbfs_status rc = make_plan(g, b, t, p, true);
+    if (rc != CBFS_OK) return rc;
+    if (!dist || !masks || !cluster_status || !workspace)
+        return fail(CBFS_E_ARG, "cbfs_run_batch: null output or workspace");
+    if (workspace_bytes < p.total) return fail(CBFS_E_WORKSPACE, "cbfs_run_batch: workspace too small");
+    return run_batch_planned(p, g, b, dist, masks, cluster_status, (char *)workspace, (hipStream_t)stream, false);
+}
+
+// ---------------------------------------------------------------------------
+// The batch with the library's own device array as its workspace, for callers
+// that cannot allocate.  `scratch` is a host-side name only: host code uses
+// the device address looked up once per device (hipGetSymbolAddress with that
+// device current), never the array's name.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[CBFS_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES];  // address of `scratch` on each device, once looked up
+}  // namespace
+
+static cbfs_status scratch_of_current_device(void **out)
+{
+    int dev = -1;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail("current device", e);
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(CBFS_E_ARG, "cbfs_run_batch_static: device index >= 64");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess)
+            return hip_fail("scratch address", e);
+        if (!ptr) return fail(CBFS_E_HIP, "cbfs_run_batch_static: scratch address is null");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return CBFS_OK;
+}
+
+extern "C" cbfs_status cbfs_run_batch_static(const cbfs_csr *g, const cbfs_batch *b, const cbfs_tuning *t,
+                                             uint32_t *dist, uint64_t *masks, int32_t *cluster_status,
+                                             void *stream)
+{
+    g_last_error.clear();
+    Plan p;
+    cbfs_status rc = make_plan(g, b, t, p, true);
+    if (rc != CBFS_OK) return rc;
+    if (!dist || !masks || !cluster_status) return fail(CBFS_E_ARG, "cbfs_run_batch_static: null output");
+    if (p.total > (size_t)CBFS_STATIC_SCRATCH_BYTES)
+        return fail(CBFS_E_WORKSPACE, "cbfs_run_batch_static: the batch needs more than the static scratch");
+    void *ws = nullptr;
+    if ((rc = scratch_of_current_device(&ws)) != CBFS_OK) return rc;
+    return run_batch_planned(p, g, b, dist, masks, cluster_status, (char *)ws, (hipStream_t)stream, true);
 }
 
 extern "C" cbfs_status cbfs_release(void)
