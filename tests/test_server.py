@@ -80,6 +80,69 @@ def test_serve_single_lane_and_late_arrivals(labels):
     assert np.all(rep.latency_s >= 0)
 
 
+class CountingExecutor(FakeExecutor):
+    """Records the queries on the device at every submission."""
+
+    def __init__(self, *a, **k):
+        super().__init__(*a, **k)
+        self.on_device = 0
+        self.peak = 0
+        self._sizes = [0] * self.lanes
+
+    def submit(self, lane, s, t):
+        super().submit(lane, s, t)
+        self._sizes[lane] = s.size
+        self.on_device += s.size
+        self.peak = max(self.peak, self.on_device)
+
+    def fetch(self, lane):
+        self.on_device -= self._sizes[lane]
+        return super().fetch(lane)
+
+
+def test_serve_memory_budget_bounds_queries_in_flight(labels):
+    """Admission by memory: with room for 100 queries on the device, no more
+    than 100 are ever in flight, batches are cut to fit, and every answer is
+    still the one the request gets alone."""
+    rp, col, cp, src, dist, masks = labels
+    nv = rp.size - 1
+    qs, qt = synth.query_pairs(nv, 2000, 21)
+    arrivals = synth.poisson_arrivals(5e5, qs.size, 21)
+    fn = lambda a, b: oracle.query_labels(dist, masks, a, b)  # noqa: E731
+    ex = CountingExecutor(fn, lanes=4, capacity=64, delay=0.002)
+    rep = server.serve(ex, qs, qt, arrivals, max_in_flight_queries=100)
+    assert not rep.rejected.any()
+    assert np.array_equal(rep.answers, fn(qs, qt))
+    assert ex.peak <= 100 and rep.max_in_flight_queries <= 100
+    assert rep.max_in_flight >= 2          # two batches fit side by side
+    assert sum(ex.submitted) == qs.size and max(ex.submitted) <= 64
+
+
+def test_serve_sheds_load_beyond_the_backlog(labels):
+    """Overload (arrivals far faster than the lanes drain): requests that find
+    the backlog full are rejected at arrival and get no answer; every admitted
+    request is answered correctly; rejections appear only under overload."""
+    rp, col, cp, src, dist, masks = labels
+    nv = rp.size - 1
+    qs, qt = synth.query_pairs(nv, 3000, 22)
+    arrivals = np.linspace(0.0, 0.003, qs.size)       # 1e6 QPS offered
+    fn = lambda a, b: oracle.query_labels(dist, masks, a, b)  # noqa: E731
+    ex = FakeExecutor(fn, lanes=1, capacity=32, delay=0.002)  # drains about 16K QPS
+    rep = server.serve(ex, qs, qt, arrivals, max_backlog=50)
+    ok = ~rep.rejected
+    assert rep.rejected.sum() > qs.size // 2
+    assert np.array_equal(rep.answers[ok], fn(qs[ok], qt[ok]))
+    assert np.all(np.isnan(rep.latency_s[rep.rejected])) and np.all(rep.latency_s[ok] >= 0)
+    assert sum(ex.submitted) == ok.sum()
+    summ = rep.summary()
+    assert summ["rejected"] == int(rep.rejected.sum()) and summ["answered"] == int(ok.sum())
+    # the same stream at a rate the lane keeps up with sheds nothing
+    slow = np.linspace(0.0, 0.6, 200)
+    rep2 = server.serve(FakeExecutor(fn, lanes=1, capacity=32, delay=0.002), qs[:200], qt[:200], slow,
+                        max_backlog=50, idle_sleep=0.0005)
+    assert not rep2.rejected.any() and np.array_equal(rep2.answers, fn(qs[:200], qt[:200]))
+
+
 @pytest.mark.gpu
 def test_gpu_server_matches_oracle_and_alone():
     import torch
