@@ -7,6 +7,9 @@ product package, and the product package never imports it.
 * ``cbfs``            -- one plain FIFO BFS per source, then the encode of the
                          subset equation (Section 3.1) re-based on the cluster
                          center (star-center storage, Section 5.3).  Plain C.
+* ``cbfs_min``        -- the same searches encoded in the paper's own form
+                         <S_v[0..d], Delta_v> (Section 3.1), for clusters of
+                         diameter d.
 * ``bfs``             -- single-source BFS (Appendix A, sequential form).
 * ``query_landmarks`` -- brute-force landmark-labeling query (Section 4.2,
                          Algorithm "Framework of Landmark Labeling", Query).
@@ -62,6 +65,8 @@ def _load():
         lib.oracle_bfs.restype = ctypes.c_int
         lib.oracle_cbfs.argtypes = [i64, P, P, i32, P, P, i32, i32, P, P, P, i32]
         lib.oracle_cbfs.restype = ctypes.c_int
+        lib.oracle_cbfs_min.argtypes = [i64, P, P, i32, P, P, i32, i32, P, P, P, i32]
+        lib.oracle_cbfs_min.restype = ctypes.c_int
         lib.oracle_query_landmarks.argtypes = [i64, P, P, i32, P, P, i64, P, P, P, i32]
         lib.oracle_query_landmarks.restype = ctypes.c_int
         lib.oracle_pair_distances.argtypes = [i64, P, P, i64, P, P, P, i32]
@@ -132,6 +137,26 @@ def cbfs(row_ptr, col, cluster_ptr, sources, R: int, W: int | None = None, nthre
     if rc != 0:
         raise ValueError(f"oracle_cbfs failed: {rc}")
     return dist, masks, status
+
+
+def cbfs_min(row_ptr, col, cluster_ptr, sources, D: int, W: int | None = None, nthreads: int = 0):
+    """The paper's cluster distance vectors <S_v[0..d], Delta_v> (Section 3.1,
+    subset equation) for clusters of diameter D.
+
+    Returns ``(delta[C][n] uint32, subsets[C][D+1][n][W] uint64, status[C] int32)``.
+    """
+    row_ptr, col, n = _csr(row_ptr, col)
+    cluster_ptr, sources, C = _clusters(cluster_ptr, sources)
+    if W is None:
+        W = words_for(cluster_ptr)
+    delta = np.empty((C, n), dtype=np.uint32)
+    subsets = np.empty((C, D + 1, n, W), dtype=np.uint64)
+    status = np.zeros(C, dtype=np.int32)
+    rc = _load().oracle_cbfs_min(n, _p(row_ptr), _p(col), C, _p(cluster_ptr), _p(sources), int(D), int(W),
+                                 _p(delta), _p(subsets), _p(status), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_cbfs_min failed: {rc}")
+    return delta, subsets, status
 
 
 def query_landmarks(row_ptr, col, cluster_ptr, sources, qs, qt, nthreads: int = 0) -> np.ndarray:

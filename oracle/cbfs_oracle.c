@@ -280,6 +280,103 @@ int oracle_cbfs(int64_t n, const int32_t *row_ptr, const int32_t *col,
     return rc;
 }
 
+/* ------------------------------------------------------------------------
+ * The cluster distance vector in the paper's own form (Section 3.1, the
+ * subset equation): for a cluster S of diameter d and every vertex v,
+ *     Delta_v  = min over s in S of delta(s, v)              (UINT32_MAX if unreachable)
+ *     S_v[i]   = {s in S : delta(s, v) = Delta_v + i},  i = 0..d
+ * (d+1 subsets; by the Fact of Section 3.1 every source lies within d of
+ * Delta_v).  Written out from one plain BFS per source: first the minimum
+ * over the sources, then each source's bit into subset delta_j(v) - Delta_v.
+ * A source at more than d beyond Delta_v, or a source that does not reach a
+ * vertex another source reaches, breaks the given diameter: the cluster's
+ * status is -5 and its outputs are UINT32_MAX and all-zero subsets.
+ * Layout: delta[C][n] uint32, subsets[C][d+1][n][W] uint64. */
+typedef struct {
+    int64_t n;
+    const int32_t *db;   /* [cnt][n] distances of sources i0 .. i0+cnt-1 */
+    int32_t cnt, i0, D, W;
+    const uint32_t *dmin;
+    uint64_t *mc;
+    int violated;
+} minenc_ctx;
+
+static void minenc_body(int64_t lo, int64_t hi, int tid, void *p)
+{
+    (void)tid;
+    minenc_ctx *e = (minenc_ctx *)p;
+    const int64_t n = e->n;
+    int bad = 0;
+    for (int64_t v = lo; v < hi; v++) {
+        const uint32_t m = e->dmin[v];
+        for (int32_t j = 0; j < e->cnt; j++) {
+            const int32_t dj = e->db[(size_t)j * (size_t)n + (size_t)v];
+            const int32_t i = e->i0 + j;
+            if (dj == UNREACHED) {
+                if (m != UINT32_MAX) bad = 1; /* another source reaches v */
+                continue;
+            }
+            const int64_t off = (int64_t)dj - (int64_t)m;
+            if (off > e->D) {
+                bad = 1;
+                continue;
+            }
+            e->mc[((size_t)off * (size_t)n + (size_t)v) * (size_t)e->W + (size_t)(i / 64)] |=
+                (uint64_t)1 << (i % 64);
+        }
+    }
+    if (bad) __atomic_store_n(&e->violated, 1, __ATOMIC_RELAXED);
+}
+
+int oracle_cbfs_min(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                    int32_t num_clusters, const int32_t *cluster_ptr, const int32_t *sources,
+                    int32_t D, int32_t W, uint32_t *delta, uint64_t *subsets, int32_t *status,
+                    int32_t nthreads)
+{
+    if (n <= 0 || num_clusters < 0 || D < 0 || W < 1) return OR_E_ARG;
+    int nt = nthreads_or_default(nthreads);
+    const int64_t P = (int64_t)D + 1;
+    int32_t *db = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * (size_t)nt);
+    if (!db) return OR_E_NOMEM;
+    int rc = OR_OK;
+    for (int32_t c = 0; c < num_clusters && rc == OR_OK; c++) {
+        const int32_t *S = sources + cluster_ptr[c];
+        const int32_t k = cluster_ptr[c + 1] - cluster_ptr[c];
+        if (k < 1 || k > 64 * W) { rc = OR_E_ARG; break; }
+        uint32_t *dc = delta + (size_t)c * (size_t)n;
+        uint64_t *mc = subsets + (size_t)c * (size_t)P * (size_t)n * (size_t)W;
+        memset(mc, 0, sizeof(uint64_t) * (size_t)P * (size_t)n * (size_t)W);
+        for (int64_t v = 0; v < n; v++) dc[v] = UINT32_MAX;
+        /* pass 1: Delta_v, the minimum over the sources */
+        for (int32_t i0 = 0; i0 < k && rc == OR_OK; i0 += nt) {
+            int32_t cnt = k - i0 < nt ? k - i0 : nt;
+            rc = bfs_batch(n, row_ptr, col, S + i0, cnt, db, nt);
+            for (int32_t j = 0; j < cnt && rc == OR_OK; j++)
+                for (int64_t v = 0; v < n; v++) {
+                    const int32_t x = db[(size_t)j * (size_t)n + (size_t)v];
+                    if (x != UNREACHED && (uint32_t)x < dc[v]) dc[v] = (uint32_t)x;
+                }
+        }
+        /* pass 2: each source's bit into subset delta_j(v) - Delta_v */
+        int violated = 0;
+        for (int32_t i0 = 0; i0 < k && rc == OR_OK; i0 += nt) {
+            int32_t cnt = k - i0 < nt ? k - i0 : nt;
+            rc = bfs_batch(n, row_ptr, col, S + i0, cnt, db, nt);
+            if (rc != OR_OK) break;
+            minenc_ctx ec = {n, db, cnt, i0, D, W, dc, mc, 0};
+            parallel_for(n, 4096, nt, minenc_body, &ec);
+            if (ec.violated) violated = 1;
+        }
+        status[c] = violated ? OR_E_RADIUS : OR_OK;
+        if (violated) {
+            for (int64_t v = 0; v < n; v++) dc[v] = UINT32_MAX;
+            memset(mc, 0, sizeof(uint64_t) * (size_t)P * (size_t)n * (size_t)W);
+        }
+    }
+    free(db);
+    return rc;
+}
+
 typedef struct {
     int64_t n;
     const int32_t *db;

@@ -106,6 +106,124 @@ def test_cbfs_equals_definition_on_apsp(name, g):
                 assert np.array_equal(masks[ci], em)
 
 
+def encode_min_from_apsp(D, cluster, d, W=None):
+    """Section 3.1's subset equation evaluated on a distance matrix:
+    Delta_v = min_s delta(s,v), S_v[i] = {s : delta(s,v) = Delta_v + i}, i <= d."""
+    n = D.shape[0]
+    k = len(cluster)
+    W = W or (k + 63) // 64
+    delta = np.full(n, U32MAX, dtype=np.uint32)
+    subs = np.zeros((d + 1, n, W), dtype=np.uint64)
+    ok = True
+    for v in range(n):
+        ds = [D[s, v] for s in cluster]
+        if all(x < 0 for x in ds):
+            continue
+        if any(x < 0 for x in ds):
+            ok = False
+            continue
+        m = min(ds)
+        delta[v] = m
+        for i, x in enumerate(ds):
+            if x - m > d:
+                ok = False
+                continue
+            subs[x - m, v, i // 64] |= np.uint64(1) << np.uint64(i % 64)
+    return delta, subs, ok
+
+
+@pytest.mark.parametrize("name,g", small_graphs())
+def test_cbfs_min_equals_definition_on_apsp(name, g):
+    """The paper's own encoding <S_v[0..d], Delta_v> against the subset
+    equation evaluated on scipy's all-pairs distances, for balls of radius h
+    (diameter at most 2h) declared with diameters 2h-1 (violations possible),
+    2h and 2h+1, and for random scattered clusters."""
+    n, s, d = g
+    rp, col, _ = oracle.clean_csr(n, s, d, flags=7)
+    D = apsp(rp, col)
+    nv = rp.size - 1
+    rng = np.random.default_rng(5)
+    for h in (1, 2, 3):
+        clusters = [oracle.cluster_around(rp, col, int(c), 64, h) for c in rng.choice(nv, size=min(8, nv), replace=False)]
+        clusters.append(rng.choice(nv, size=min(10, nv), replace=False).astype(np.int32))
+        cp = np.zeros(len(clusters) + 1, np.int32)
+        cp[1:] = np.cumsum([x.size for x in clusters])
+        for dd in (2 * h - 1, 2 * h, 2 * h + 1):
+            delta, subs, status = oracle.cbfs_min(rp, col, cp, np.concatenate(clusters), dd)
+            for ci, cl in enumerate(clusters):
+                ed, es, ok = encode_min_from_apsp(D, list(cl), dd)
+                assert (status[ci] == 0) == ok, (name, h, dd, ci)
+                if ok:
+                    assert np.array_equal(delta[ci], ed)
+                    assert np.array_equal(subs[ci], es)
+                else:
+                    assert (delta[ci] == U32MAX).all() and not subs[ci].any()
+
+
+def test_cbfs_min_path_closed_form():
+    """Path 0-1-...-39, cluster = the consecutive vertices a..b: Delta_v is the
+    distance to the nearer end of [a, b] (0 inside), and source s_j sits in
+    subset |s_j - v| - Delta_v."""
+    n, a, b = 40, 12, 17
+    rp, col = csr_of(n, [(i, i + 1) for i in range(n - 1)])
+    S = list(range(a, b + 1))
+    dd = b - a
+    delta, subs, st = oracle.cbfs_min(rp, col, [0, len(S)], S, dd)
+    assert st[0] == 0
+    for v in range(n):
+        m = a - v if v < a else (v - b if v > b else 0)
+        assert delta[0, v] == m
+        for j, sj in enumerate(S):
+            i = abs(sj - v) - m
+            assert (int(subs[0, i, v, 0]) >> j) & 1, (v, j)
+    # each source exactly once per vertex
+    total = np.zeros(n, np.int64)
+    for i in range(dd + 1):
+        total += np.array([bin(int(x)).count("1") for x in subs[0, i, :, 0]])
+    assert (total == len(S)).all()
+
+
+def test_cbfs_min_complete_graph_and_invariants():
+    """K_n with a cluster of k vertices: a member sees itself at subset 0 and
+    the others at 1; a non-member sees all k at subset 0 (Delta = 1)."""
+    n, k = 12, 5
+    rp, col = csr_of(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
+    S = [3, 0, 7, 9, 11]
+    delta, subs, st = oracle.cbfs_min(rp, col, [0, k], S, 1)
+    assert st[0] == 0
+    full = (1 << k) - 1
+    for v in range(n):
+        if v in S:
+            j = S.index(v)
+            assert delta[0, v] == 0 and subs[0, 0, v, 0] == 1 << j and subs[0, 1, v, 0] == full ^ (1 << j)
+        else:
+            assert delta[0, v] == 1 and subs[0, 0, v, 0] == full and subs[0, 1, v, 0] == 0
+    # diameter 0 for a cluster of two distinct vertices is broken
+    _, _, st0 = oracle.cbfs_min(rp, col, [0, 2], S[:2], 0)
+    assert st0[0] == -5
+
+
+def test_cbfs_min_agrees_with_center_relative_on_stars():
+    """Both encodings of one search: the center's bit sits in subset j_c, and
+    then d(c,v) = Delta_v + j_c and M[o] = S_v[j_c + o] (the re-basing of the
+    star storage of Section 5.3)."""
+    n, s, d = synth.rmat_edges(9, 8, seed=3)
+    rp, col, _ = oracle.clean_csr(n, s, d)
+    cp, src = oracle.build_clusters(rp, col, oracle.top_degree(rp, 6), 64, 1)
+    delta, subs, st = oracle.cbfs_min(rp, col, cp, src, 2)
+    dist, masks, st2 = oracle.cbfs(rp, col, cp, src, R=2)
+    assert (st == 0).all() and (st2 == 0).all()
+    for c in range(cp.size - 1):
+        reach = delta[c] != U32MAX
+        jc = np.argmax((subs[c, :, :, 0] & np.uint64(1)) != 0, axis=0)
+        assert np.array_equal(dist[c][reach], delta[c][reach] + jc[reach])
+        for v in np.nonzero(reach)[0][:400]:
+            for o in range(-2, 3):
+                i = jc[v] + o
+                want = subs[c, i, v, 0] if 0 <= i <= 2 else 0
+                assert masks[c, o + 2, v, 0] == want
+
+
 def test_path_graph_closed_form():
     n = 40
     rp, col = csr_of(n, [(i, i + 1) for i in range(n - 1)])
