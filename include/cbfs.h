@@ -110,6 +110,22 @@ cbfs_status cbfs_build_csr(int64_t n_in, int64_t num_edges, const int64_t *src, 
  * 1..256), CBFS_E_WORKSPACE (capacity), CBFS_E_NOMEM.
  * ------------------------------------------------------------------------ */
 cbfs_status cbfs_top_degree(int64_t n, const int32_t *row_ptr, int32_t count, int32_t *out);
+
+/* cbfs_select_landmarks: clusters of landmarks as Section 4.2 ("Selecting
+ * Landmarks in Clusters") builds them for a cluster size k and diameter d:
+ * the unmarked vertex of highest degree is a center; among its unmarked
+ * vertices within floor(d/2) hops the k-1 of highest degree join it; every
+ * vertex of the cluster is marked and never selected again; repeated until
+ * num_clusters clusters exist or every vertex is marked.  Degree ties go to
+ * the lower id.  Each cluster lists its center first, then its members by
+ * descending degree.  Outputs cluster_ptr[num_clusters+1] and
+ * sources[sources_capacity] (host; num_clusters*k suffices) and
+ * *num_selected, the clusters made.  Every cluster has diameter <= d.
+ * Errors: CBFS_E_ARG, CBFS_E_TOO_MANY_SOURCES (k outside 1..256),
+ * CBFS_E_WORKSPACE (capacity), CBFS_E_NOMEM. */
+cbfs_status cbfs_select_landmarks(int64_t n, const int32_t *row_ptr, const int32_t *col, int32_t num_clusters,
+                                  int32_t k, int32_t diameter, int32_t *cluster_ptr, int32_t *sources,
+                                  int64_t sources_capacity, int32_t *num_selected);
 cbfs_status cbfs_select_clusters(int64_t n, const int32_t *row_ptr, const int32_t *col,
                                  int32_t num_centers, const int32_t *centers, int32_t k_max,
                                  int32_t hops, int32_t *cluster_ptr, int32_t *sources,
@@ -124,6 +140,12 @@ cbfs_status cbfs_select_clusters(int64_t n, const int32_t *row_ptr, const int32_
  *   dist[c][v]            = d(s_0, v), or CBFS_UNREACHED
  *   masks[c][o + R][v][w] = word w of the set {i : d(s_i, v) = d(s_0, v) + o},
  *                           o in [-R, R]; all zero where dist is CBFS_UNREACHED
+ * or, with encoding CBFS_ENCODE_MIN and radius = the cluster diameter d, the
+ * paper's cluster distance vector <S_v[0..d], Delta_v> (Section 3.1):
+ *   dist[c][v]            = Delta_v = min_i d(s_i, v), or CBFS_UNREACHED
+ *   masks[c][j][v][w]     = word w of {i : d(s_i, v) = Delta_v + j}, j in [0, d]
+ * (a source that reaches v more than d beyond Delta_v, or not at all while
+ * another source does, is a violation of the given diameter).
  *   cluster_status[c]     = CBFS_OK, or CBFS_E_RADIUS when some source of c
  *                           lies at an offset outside [-R, R] at some vertex
  *                           (or reaches a vertex the center does not), or
@@ -150,12 +172,23 @@ typedef struct {
     const int32_t *col;     /* device [m]                             */
 } cbfs_csr;
 
+enum {
+    CBFS_ENCODE_CENTER = 0,  /* dist = d(s_0, v), planes for offsets -R..R (2R+1), the
+                                star storage of Section 5.3                           */
+    CBFS_ENCODE_MIN = 1      /* the paper's own form, Section 3.1: dist = Delta_v =
+                                min over the sources of d(s, v), and plane i the subset
+                                S_v[i] = {s : d(s, v) = Delta_v + i}, i = 0..d, for a
+                                cluster of diameter d given in `radius` (d+1 planes)  */
+};
+
 typedef struct {
     int32_t num_clusters;       /* C >= 1                                          */
     const int32_t *cluster_ptr; /* host [C+1], cluster_ptr[0] = 0, non-decreasing  */
     const int32_t *sources;     /* host; cluster c = sources[cluster_ptr[c] ..
                                    cluster_ptr[c+1]), its first entry the center   */
-    int32_t radius;             /* R >= 0: 2R+1 offset planes                      */
+    int32_t radius;             /* CBFS_ENCODE_CENTER: R >= 0, 2R+1 offset planes;
+                                   CBFS_ENCODE_MIN: the diameter d >= 0, d+1 planes */
+    int32_t encoding;           /* CBFS_ENCODE_* (0: center-relative)              */
 } cbfs_batch;
 
 enum {
@@ -198,7 +231,8 @@ size_t cbfs_run_batch_workspace_size(const cbfs_csr *g, const cbfs_batch *b, con
 
 /*
  *   dist           device [C][n]          uint32 output
- *   masks          device [C][2R+1][n][W] uint64 output
+ *   masks          device [C][P][n][W]    uint64 output, P = 2R+1 (center) or
+ *                                         d+1 (min, d = radius)
  *   cluster_status device [C]             int32 output
  *   workspace      device, workspace_bytes >= cbfs_run_batch_workspace_size(...)
  * Ordering: everything is enqueued on `stream`.  In CBFS_MODE_PERSISTENT the

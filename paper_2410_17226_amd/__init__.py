@@ -9,8 +9,9 @@ from __future__ import annotations
 
 from ._binding import (  # noqa: F401
     CBFS_OK, CBFS_E_RADIUS, CBFS_MODE_AUTO, CBFS_MODE_HOST_LOOP, CBFS_MODE_PERSISTENT,
-    CBFS_CSR_ALL, UNREACHED, CbfsError, LIB_PATH, load, exported_symbols,
-    build_csr, top_degree, select_clusters,
+    CBFS_CSR_ALL, CBFS_ENCODE_CENTER, CBFS_ENCODE_MIN, UNREACHED, CbfsError, LIB_PATH, load, exported_symbols,
+    planes_of,
+    build_csr, top_degree, select_clusters, select_landmarks,
     Tuning, run_batch_workspace_size, run_batch, autotune, run_batch_static, STATIC_SCRATCH_BYTES,
     labels_pack, query_batch, status_string,
     last_run_stats, profile_enable, profile_read, KERNEL_KINDS, release,

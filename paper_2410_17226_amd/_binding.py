@@ -16,6 +16,8 @@ CBFS_MODE_AUTO = 0
 CBFS_MODE_HOST_LOOP = 1
 CBFS_MODE_PERSISTENT = 2
 CBFS_CSR_ALL = 15
+CBFS_ENCODE_CENTER = 0
+CBFS_ENCODE_MIN = 1
 UNREACHED = 0xFFFFFFFF
 
 SYMBOLS = [
@@ -23,7 +25,7 @@ SYMBOLS = [
     "cbfs_select_clusters", "cbfs_run_batch_workspace_size", "cbfs_run_batch",
     "cbfs_last_run_stats", "cbfs_profile_enable", "cbfs_profile_read",
     "cbfs_labels_pack", "cbfs_query_batch", "cbfs_autotune_workspace_size", "cbfs_autotune",
-    "cbfs_release", "cbfs_run_batch_static",
+    "cbfs_release", "cbfs_run_batch_static", "cbfs_select_landmarks",
 ]
 KERNEL_KINDS = ["tiles", "init", "seed", "push", "pull", "finalize", "persistent", "labels", "query"]
 
@@ -43,7 +45,7 @@ class _Csr(ctypes.Structure):
 
 class _Batch(ctypes.Structure):
     _fields_ = [("num_clusters", ctypes.c_int32), ("cluster_ptr", ctypes.c_void_p),
-                ("sources", ctypes.c_void_p), ("radius", ctypes.c_int32)]
+                ("sources", ctypes.c_void_p), ("radius", ctypes.c_int32), ("encoding", ctypes.c_int32)]
 
 
 class _Tuning(ctypes.Structure):
@@ -118,6 +120,8 @@ def load():
     lib.cbfs_top_degree.restype = i32
     lib.cbfs_select_clusters.argtypes = [i64, P, P, i32, P, i32, i32, P, P, i64]
     lib.cbfs_select_clusters.restype = i32
+    lib.cbfs_select_landmarks.argtypes = [i64, P, P, i32, i32, i32, P, P, i64, P]
+    lib.cbfs_select_landmarks.restype = i32
     lib.cbfs_run_batch_workspace_size.argtypes = [P, P, P]
     lib.cbfs_run_batch_workspace_size.restype = sz
     lib.cbfs_run_batch.argtypes = [P, P, P, P, P, P, P, sz, P]
@@ -218,6 +222,22 @@ def select_clusters(row_ptr, col, centers, k_max: int, hops: int):
     return cptr, src[: cptr[-1]].copy()
 
 
+def select_landmarks(row_ptr, col, num_clusters: int, k: int, diameter: int):
+    """``cbfs_select_landmarks``: the paper's degree-prioritised clusters with
+    marking; returns (cluster_ptr int32[C+1], sources int32[...]), C <= num_clusters."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    cptr = np.empty(int(num_clusters) + 1, dtype=np.int32)
+    cap = max(1, int(num_clusters) * int(k))
+    src = np.empty(cap, dtype=np.int32)
+    made = ctypes.c_int32(0)
+    _check(load().cbfs_select_landmarks(row_ptr.size - 1, _np_ptr(row_ptr), _np_ptr(col), int(num_clusters), int(k),
+                                        int(diameter), _np_ptr(cptr), _np_ptr(src), cap, ctypes.byref(made)),
+           "cbfs_select_landmarks")
+    C = made.value
+    return cptr[: C + 1].copy(), src[: cptr[C]].copy()
+
+
 # --------------------------------------------------------------------------- device entry points
 def _torch():
     import torch
@@ -235,19 +255,24 @@ def _dptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, tuning):
+def planes_of(R: int, encoding: int = CBFS_ENCODE_CENTER) -> int:
+    return R + 1 if encoding == CBFS_ENCODE_MIN else 2 * R + 1
+
+
+def _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, tuning, encoding=CBFS_ENCODE_CENTER):
     cluster_ptr = np.ascontiguousarray(cluster_ptr, dtype=np.int32)
     sources = np.ascontiguousarray(sources, dtype=np.int32)
     if cluster_ptr.size >= 1 and int(cluster_ptr[-1]) > sources.size:
         raise ValueError("cluster_ptr[-1] exceeds the number of sources")
     g = _Csr(row_ptr_d.numel() - 1, col_d.numel(), row_ptr_d.data_ptr(), col_d.data_ptr())
-    b = _Batch(cluster_ptr.size - 1, _np_ptr(cluster_ptr), _np_ptr(sources), int(R))
+    b = _Batch(cluster_ptr.size - 1, _np_ptr(cluster_ptr), _np_ptr(sources), int(R), int(encoding))
     t = tuning._c() if tuning is not None else None
     return g, b, t, cluster_ptr, sources
 
 
-def run_batch_workspace_size(row_ptr_d, col_d, cluster_ptr, sources, R: int, tuning: Tuning | None = None) -> int:
-    g, b, t, _keep1, _keep2 = _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, tuning)
+def run_batch_workspace_size(row_ptr_d, col_d, cluster_ptr, sources, R: int, tuning: Tuning | None = None,
+                             encoding: int = CBFS_ENCODE_CENTER) -> int:
+    g, b, t, _keep1, _keep2 = _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, tuning, encoding)
     return int(load().cbfs_run_batch_workspace_size(ctypes.byref(g), ctypes.byref(b),
                                                     ctypes.byref(t) if t is not None else None))
 
@@ -258,24 +283,26 @@ def words_for(cluster_ptr) -> int:
 
 
 def run_batch(row_ptr_d, col_d, cluster_ptr, sources, R: int, tuning: Tuning | None = None,
-              out=None, workspace=None, stream=None):
+              out=None, workspace=None, stream=None, encoding: int = CBFS_ENCODE_CENTER):
     """``cbfs_run_batch`` on device CSR tensors (int32).
 
     Returns ``(dist, masks, status)`` as torch tensors on the graph's device:
-    dist int32[C][n] (bit pattern of uint32), masks int64[C][2R+1][n][W] (bit
-    pattern of uint64), status int32[C].  ``out`` may pass preallocated tensors
-    of those shapes, ``workspace`` a uint8 tensor of at least the required size.
+    dist int32[C][n] (bit pattern of uint32), masks int64[C][P][n][W] (bit
+    pattern of uint64; P = 2R+1, or R+1 with encoding CBFS_ENCODE_MIN where R
+    is the cluster diameter), status int32[C].  ``out`` may pass preallocated
+    tensors of those shapes, ``workspace`` a uint8 tensor of at least the
+    required size.
     """
     torch = _torch()
     lib = load()
-    g, b, t, cptr, srcs = _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, tuning)
+    g, b, t, cptr, srcs = _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, tuning, encoding)
     C = cptr.size - 1
     n = row_ptr_d.numel() - 1
     W = words_for(cptr)
     dev = row_ptr_d.device
     if out is None:
         dist = torch.empty((C, n), dtype=torch.int32, device=dev)
-        masks = torch.empty((C, 2 * R + 1, n, W), dtype=torch.int64, device=dev)
+        masks = torch.empty((C, planes_of(R, encoding), n, W), dtype=torch.int64, device=dev)
         status = torch.empty(C, dtype=torch.int32, device=dev)
     else:
         dist, masks, status = out
@@ -297,20 +324,20 @@ STATIC_SCRATCH_BYTES = 64 << 20
 
 
 def run_batch_static(row_ptr_d, col_d, cluster_ptr, sources, R: int, tuning: Tuning | None = None,
-                     out=None, stream=None):
+                     out=None, stream=None, encoding: int = CBFS_ENCODE_CENTER):
     """``cbfs_run_batch_static``: ``run_batch`` with the library's own device
     scratch array as the workspace (no allocation by the library).  ``out``
     may pass preallocated output tensors; otherwise they are created here."""
     torch = _torch()
     lib = load()
-    g, b, t, cptr, srcs = _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, tuning)
+    g, b, t, cptr, srcs = _batch_structs(row_ptr_d, col_d, cluster_ptr, sources, R, tuning, encoding)
     C = cptr.size - 1
     n = row_ptr_d.numel() - 1
     if out is None:
         W = words_for(cptr)
         dev = row_ptr_d.device
         out = (torch.empty((C, n), dtype=torch.int32, device=dev),
-               torch.empty((C, 2 * R + 1, n, W), dtype=torch.int64, device=dev),
+               torch.empty((C, planes_of(R, encoding), n, W), dtype=torch.int64, device=dev),
                torch.empty(C, dtype=torch.int32, device=dev))
     dist, masks, status = out
     rc = lib.cbfs_run_batch_static(ctypes.byref(g), ctypes.byref(b), ctypes.byref(t) if t is not None else None,

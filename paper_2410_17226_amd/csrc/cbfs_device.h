@@ -82,8 +82,14 @@ struct OutArgs {
     uint32_t *dist;           // [C][n]
     uint64_t *masks;          // [C][P][n][WC]
     int32_t *status;          // [C]
-    int32_t R;
+    int32_t R;                // center-relative: the offset radius; min-relative: the diameter d
+    int32_t minrel;           // 1: min-relative encode (P = d + 1), 0: center-relative (P = 2R + 1)
 };
+
+__host__ __device__ inline int64_t planes_of(const OutArgs &o)
+{
+    return o.minrel ? (int64_t)o.R + 1 : 2 * (int64_t)o.R + 1;
+}
 
 __device__ __forceinline__ uint64_t *cur_buf(const SlotArgs &s, int round) { return (round & 1) ? s.B : s.A; }
 __device__ __forceinline__ uint64_t *nxt_buf(const SlotArgs &s, int round) { return (round & 1) ? s.A : s.B; }
@@ -181,7 +187,7 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
     }
     if (!any_new) return;
     const int32_t R = o.R;
-    const int64_t P = 2 * (int64_t)R + 1;
+    const int64_t P = planes_of(o);
     uint32_t *dslot = o.dist + (size_t)c * (size_t)n + (size_t)v;
     auto plane = [&](int64_t p) { return o.masks + (((size_t)c * P + (size_t)p) * (size_t)n + (size_t)v) * WC; };
     auto put = [&](int64_t p, const uint64_t *val) {
@@ -196,6 +202,20 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
     };
     auto violate = [&]() { atomicExch(o.status + c, E_RADIUS); };
 
+    if (o.minrel) {
+        // the paper's own form (Section 3.1): Delta_v is the round the first
+        // bit arrives, and the bits of round i go to subset i - Delta_v <= d
+        if (!any_prev) {
+            *dslot = (uint32_t)i;
+            put(0, nw);
+            for (int32_t p = 1; p <= R; p++) put_zero(p);
+        } else {
+            const int32_t j = i - (int32_t)dold;
+            if (j > R) violate();
+            else put(j, nw);
+        }
+        return;
+    }
     if (prev[0] & 1ull) {
         const int32_t k = i - (int32_t)dold;
         if (k < 1 || k > R) {

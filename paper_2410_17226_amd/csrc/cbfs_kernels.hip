@@ -122,7 +122,7 @@ __global__ __launch_bounds__(BLOCK) void k_scrub(OutArgs o, int64_t n, int32_t W
     const int64_t tid = (int64_t)blockIdx.x * BLOCK + threadIdx.x, stride = (int64_t)gridDim.x * BLOCK;
     uint32_t *d = o.dist + (size_t)c * (size_t)n;
     for (int64_t v = tid; v < n; v += stride) d[v] = UNREACHED;
-    const int64_t words = (2 * (int64_t)o.R + 1) * n * WC;
+    const int64_t words = planes_of(o) * n * WC;
     uint64_t *m = o.masks + (size_t)c * (size_t)words;
     for (int64_t k = tid; k < words; k += stride) m[k] = 0;
 }

@@ -539,11 +539,20 @@ __device__ __forceinline__ uint64_t dpp64(uint64_t x)
 template <int W>
 __device__ __forceinline__ void seg_or_scan(uint64_t (&x)[W], int lane, int first)
 {
+    // one AND-OR per dword: the lane's mask (all ones when the shifted lane
+    // lies in its segment) is formed once per level
     auto level = [&](auto ctrl, auto rmask, bool take) {
+        if (__ballot(take) == 0) return;  // no lane's segment reaches this far: the level is a no-op
+        uint32_t m = take ? 0xFFFFFFFFu : 0u;
+        asm("" : "+v"(m));  // an opaque mask: keeps AND-OR from being turned back into selects
 #pragma unroll
         for (int w = 0; w < W; w++) {
-            const uint64_t y = dpp64<decltype(ctrl)::value, decltype(rmask)::value>(x[w]);
-            x[w] |= take ? y : 0ull;
+            const uint32_t lo = (uint32_t)x[w], hi = (uint32_t)(x[w] >> 32);
+            const uint32_t ylo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, decltype(ctrl)::value,
+                                                                       decltype(rmask)::value, 0xF, true);
+            const uint32_t yhi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, decltype(ctrl)::value,
+                                                                       decltype(rmask)::value, 0xF, true);
+            x[w] = ((uint64_t)((yhi & m) | hi) << 32) | (uint64_t)((ylo & m) | lo);
         }
     };
     using c1 = std::integral_constant<int, 0x111>;
@@ -557,8 +566,8 @@ __device__ __forceinline__ void seg_or_scan(uint64_t (&x)[W], int lane, int firs
     level(c2{}, all{}, lane - 2 >= first);
     level(c4{}, all{}, lane - 4 >= first);
     level(c8{}, all{}, lane - 8 >= first);
-    level(b15{}, std::integral_constant<int, 0xA>{}, (lane & ~15) - 1 >= first);
-    level(b31{}, std::integral_constant<int, 0xC>{}, 31 >= first);
+    level(b15{}, std::integral_constant<int, 0xA>{}, (lane & 16) != 0 && (lane & ~15) - 1 >= first);
+    level(b31{}, std::integral_constant<int, 0xC>{}, lane >= 32 && 31 >= first);
 }
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t x, int src)
@@ -1092,15 +1101,16 @@ __device__ void pull_tile(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
 }
 
 // ---------------------------------------------------------------------------
-// Finalize: a vertex never reached by the center gets CBFS_UNREACHED and zero
-// masks (a cluster source reaching it is a radius violation); a vertex reached
-// by the center but not by every source of the cluster is a violation too.
+// Finalize: a vertex never reached by the center (center-relative) or by any
+// source (min-relative) gets CBFS_UNREACHED and zero masks (a cluster source
+// reaching it is a radius violation); a vertex reached but not by every
+// source of the cluster is a violation too.
 // ---------------------------------------------------------------------------
 template <int W, int WC>
 __device__ __forceinline__ void finalize_part(const SlotArgs &s, int64_t n, const GroupDesc &g, const OutArgs &o,
                                               int64_t tid, int64_t stride)
 {
-    const int64_t P = 2 * (int64_t)o.R + 1;
+    const int64_t P = planes_of(o);
     for (int64_t v = tid; v < n; v += stride) {
         uint64_t sv[W];
         load_words<W>(s.seen + (size_t)v * W, sv);
@@ -1115,7 +1125,9 @@ __device__ __forceinline__ void finalize_part(const SlotArgs &s, int64_t n, cons
                 any |= sc[x] != 0;
                 full &= sc[x] == g.full[j * WC + x];
             }
-            if (!(sc[0] & 1ull)) {
+            // unreached: by the center (center-relative), or by every source
+            // (min-relative, where Delta_v needs only one)
+            if (o.minrel ? !any : !(sc[0] & 1ull)) {
                 if (any) atomicExch(o.status + c, E_RADIUS);
                 o.dist[(size_t)c * n + v] = UNREACHED;
                 for (int64_t p = 0; p < P; p++) {

@@ -97,6 +97,7 @@ void prof_end(void *token) { delete (ProfScope *)token; }
 struct Plan {
     int64_t n = 0, m = 0;
     int32_t C = 0, R = 0;
+    int32_t minrel = 0;   // CBFS_ENCODE_MIN: R is the cluster diameter, R + 1 planes
     int32_t WC = 1;       // words per cluster (output W)
     int32_t W = 1;        // words per vertex in a group
     int32_t per_group = 1;
@@ -133,6 +134,8 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
     if (b->num_clusters < 1 || !b->cluster_ptr || !b->sources)
         return fail(CBFS_E_ARG, "cbfs_run_batch: empty batch or null cluster arrays");
     if (b->radius < 0 || b->radius > 1024) return fail(CBFS_E_ARG, "cbfs_run_batch: radius outside [0, 1024]");
+    if (b->encoding != CBFS_ENCODE_CENTER && b->encoding != CBFS_ENCODE_MIN)
+        return fail(CBFS_E_ARG, "cbfs_run_batch: unknown encoding");
     if (b->cluster_ptr[0] != 0) return fail(CBFS_E_ARG, "cbfs_run_batch: cluster_ptr[0] != 0");
     int32_t kmax = 0;
     for (int32_t c = 0; c < b->num_clusters; c++) {
@@ -158,6 +161,7 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
     p.m = g->m;
     p.C = b->num_clusters;
     p.R = b->radius;
+    p.minrel = b->encoding == CBFS_ENCODE_MIN ? 1 : 0;
     p.total_sources = b->cluster_ptr[p.C];
     p.WC = (kmax + 63) / 64;
     // defaults: wide groups share one CSR pass among many clusters (16 words
@@ -398,7 +402,7 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
     const GraphArgs gr = graph_args(p, g, ws);
     const int32_t *d_cptr = (const int32_t *)(ws + p.off_cptr);
     const int32_t *d_src = (const int32_t *)(ws + p.off_src);
-    OutArgs o{dist, masks, status, p.R};
+    OutArgs o{dist, masks, status, p.R, p.minrel};
     hipError_t e;
     cbfs_run_stats &rs = g_last.host;
     const SlotArgs s = slot_at(p, ws, 0);
@@ -473,7 +477,7 @@ static cbfs_status run_persistent(const Plan &p, const cbfs_csr *g, uint32_t *di
     if (p.slots > blocks) return fail(CBFS_E_ARG, "cbfs_run_batch: more group slots than resident blocks");
     PersistArgs a{};
     a.gr = graph_args(p, g, ws);
-    a.o = OutArgs{dist, masks, status, p.R};
+    a.o = OutArgs{dist, masks, status, p.R, p.minrel};
     a.slots = (const SlotArgs *)(ws + p.off_slotdesc);
     a.groups = (const GroupDesc *)(ws + p.off_groupdesc);
     a.num_groups = p.groups;
@@ -551,24 +555,25 @@ static cbfs_status run_batch_planned(const Plan &p, const cbfs_csr *g, const cbf
 
     // one upload of the batch tables through a pinned staging buffer (no wait
     // for earlier work on the stream); the host arrays are not used afterwards
-    std::vector<char> stage(p.off_slots, 0);
-    std::memcpy(stage.data() + p.off_cptr, b->cluster_ptr, sizeof(int32_t) * (size_t)(p.C + 1));
-    std::memcpy(stage.data() + p.off_src, b->sources, sizeof(int32_t) * (size_t)p.total_sources);
+    // the tables occupy workspace bytes [off_cptr, off_ctl)
+    const size_t lo = p.off_cptr, hi = p.off_ctl;
+    std::vector<char> stage(hi - lo, 0);
+    std::memcpy(stage.data() + (p.off_cptr - lo), b->cluster_ptr, sizeof(int32_t) * (size_t)(p.C + 1));
+    std::memcpy(stage.data() + (p.off_src - lo), b->sources, sizeof(int32_t) * (size_t)p.total_sources);
     for (int32_t sl = 0; sl < p.slots; sl++) {
         SlotArgs s = slot_at(p, ws, sl);
-        std::memcpy(stage.data() + p.off_slotdesc + sizeof(SlotArgs) * sl, &s, sizeof(SlotArgs));
+        std::memcpy(stage.data() + (p.off_slotdesc - lo) + sizeof(SlotArgs) * sl, &s, sizeof(SlotArgs));
     }
     for (int32_t grp = 0; grp < p.groups; grp++) {
         GroupDesc d = group_desc(p, b, grp);
-        std::memcpy(stage.data() + p.off_groupdesc + sizeof(GroupDesc) * grp, &d, sizeof(GroupDesc));
+        std::memcpy(stage.data() + (p.off_groupdesc - lo) + sizeof(GroupDesc) * grp, &d, sizeof(GroupDesc));
     }
     hipError_t e;
-    const size_t lo = p.off_cptr, hi = p.off_ctl;
     if (!no_alloc) {
-        if ((rc = staged_upload(ws + lo, stage.data() + lo, hi - lo, st)) != CBFS_OK) return rc;
+        if ((rc = staged_upload(ws + lo, stage.data(), hi - lo, st)) != CBFS_OK) return rc;
     } else {
         // pageable source: wait for the copy before `stage` goes away
-        if ((e = hipMemcpyAsync(ws + lo, stage.data() + lo, hi - lo, hipMemcpyHostToDevice, st)) != hipSuccess)
+        if ((e = hipMemcpyAsync(ws + lo, stage.data(), hi - lo, hipMemcpyHostToDevice, st)) != hipSuccess)
             return hip_fail("batch upload", e);
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail("batch upload wait", e);
     }
@@ -588,7 +593,7 @@ static cbfs_status run_batch_planned(const Plan &p, const cbfs_csr *g, const cbf
     }
     if (rc != CBFS_OK) return rc;
     // clusters whose status is not CBFS_OK: defined outputs (UNREACHED, zero masks)
-    const OutArgs o{dist, masks, cluster_status, p.R};
+    const OutArgs o{dist, masks, cluster_status, p.R, p.minrel};
     if ((e = PROF(CBFS_KERNEL_FINALIZE, st, launch_scrub(o, p.n, p.C, p.WC, abort_flag, st))) != hipSuccess)
         return hip_fail("status scrub", e);
     return CBFS_OK;

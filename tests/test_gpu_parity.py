@@ -36,15 +36,16 @@ def prepare(n, s, d, centers_fn, k, hops):
     return (rp, col, cp, src), (orp, ocol, ocp, osrc)
 
 
-def gpu_cbfs(rp, col, cp, src, R, tuning=None):
+def gpu_cbfs(rp, col, cp, src, R, tuning=None, encoding=0):
     torch = _torch()
     import paper_2410_17226_amd as P
-    print(f"[gpu_cbfs] n={rp.size - 1} m={col.size} C={cp.size - 1} R={R} tuning={tuning}", flush=True)
+    print(f"[gpu_cbfs] n={rp.size - 1} m={col.size} C={cp.size - 1} R={R} enc={encoding} tuning={tuning}",
+          flush=True)
     rp_d = torch.from_numpy(rp).cuda()
     col_d = torch.from_numpy(col if col.size else np.zeros(1, np.int32)).cuda()
     if col.size == 0:
         col_d = col_d[:0]
-    dist, masks, st = P.run_batch(rp_d, col_d, cp, src, R, tuning)
+    dist, masks, st = P.run_batch(rp_d, col_d, cp, src, R, tuning, encoding=encoding)
     torch.cuda.synchronize()
     return (dist.cpu().numpy().view(np.uint32), masks.cpu().numpy().view(np.uint64), st.cpu().numpy())
 
@@ -174,6 +175,63 @@ def test_parity_radius_zero():
         ref = oracle.cbfs(rp, col, cp2, src2, R=0)
         assert ref[2][-1] == oracle.E_RADIUS and (ref[2][:-1] == 0).all()
         assert_same(gpu, ref, f"R=0 {tun}")
+
+
+MIN_TUNINGS = [None, dict(alpha=-1.0), dict(force_pull=1), dict(mode=1, force_pull=1, gamma=1e-9),
+               dict(mode=1, group_words=16), dict(mode=2, concurrent_groups=4, group_words=1),
+               dict(mode=1, alpha=-1.0, hub_arcs=1)]
+MIN_IDS = ["default", "push", "pull", "pull_wave", "w16", "persistent", "hub_push"]
+
+
+def min_cases():
+    out = []
+    for seed in range(2):
+        out.append(("gnp", lambda seed=seed: synth.random_graph(150, 0.04, seed + 40)))
+        out.append(("tree", lambda seed=seed: synth.random_tree(150, seed + 40)))
+    out.append(("grid", lambda: synth.grid_edges(25, 0.1, seed=4)))
+    out.append(("rmat10", lambda: synth.rmat_edges(10, 16, seed=9)))
+    return out
+
+
+@pytest.mark.parametrize("name,gen", min_cases(), ids=[c[0] for c in min_cases()])
+@pytest.mark.parametrize("tun", MIN_TUNINGS, ids=MIN_IDS)
+def test_parity_min_relative(name, gen, tun):
+    """The paper's own encoding <S_v[0..d], Delta_v> (Section 3.1): balls of
+    radius h (diameter at most 2h) declared with d = 2h - 1 (violations),
+    2h and 2h + 1, and scattered clusters (violations), bit for bit against
+    the oracle, statuses and cleared outputs included."""
+    import paper_2410_17226_amd as P
+    n, s, d = gen()
+    rp, col, _ = P.build_csr(n, s, d)
+    orp, ocol, _ = oracle.clean_csr(n, s, d)
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+    nv = rp.size - 1
+    rng = np.random.default_rng(17)
+    for h in (1, 2, 3):
+        centers = rng.choice(nv, size=min(6, nv), replace=False).astype(np.int32)
+        cp, src = P.select_clusters(rp, col, centers, 64, h)
+        extra = rng.choice(nv, size=min(9, nv), replace=False).astype(np.int32)
+        cp = np.concatenate([cp, [cp[-1] + extra.size]]).astype(np.int32)
+        src = np.concatenate([src, extra]).astype(np.int32)
+        for dd in (2 * h - 1, 2 * h, 2 * h + 1):
+            gpu = gpu_cbfs(rp, col, cp, src, dd, tuning_of(tun), encoding=P.CBFS_ENCODE_MIN)
+            ref = oracle.cbfs_min(orp, ocol, cp, src, dd)
+            assert_same(gpu, ref, f"{name} h={h} d={dd}")
+
+
+def test_parity_min_relative_wide_clusters():
+    """Clusters of 150 and 256 sources (2 and 4 words) in the min-relative form."""
+    import paper_2410_17226_amd as P
+    n, s, d = synth.rmat_edges(11, 16, seed=13)
+    rp, col, _ = P.build_csr(n, s, d)
+    centers = oracle.top_degree(rp, 3)
+    for k in (150, 256):
+        cp, src = P.select_clusters(rp, col, centers, k, 1)
+        for tun in (None, dict(force_pull=1), dict(alpha=-1.0)):
+            gpu = gpu_cbfs(rp, col, cp, src, 2, tuning_of(tun, (k + 63) // 64), encoding=P.CBFS_ENCODE_MIN)
+            ref = oracle.cbfs_min(rp, col, cp, src, 2)
+            assert (ref[2] == 0).all()
+            assert_same(gpu, ref, f"k={k} {tun}")
 
 
 @pytest.mark.parametrize("tun", TUNINGS, ids=TUNING_IDS)
