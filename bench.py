@@ -35,6 +35,7 @@ METRIC = "source-GTEPS (sources×edges/s) + %HBM roofline; batched vs plain; que
 KERNEL_SOURCES = ["cbfs_device.h", "cbfs_round.h", "cbfs_kernels.hip", "cbfs_kernels.h"]
 WORKLOAD_NAMES = {
     "rmat22": ("rmat22_batch256", "R-MAT scale 22 ef 16 (0.57,0.19,0.19,0.05)"),
+    "rmat14": ("rmat14_one_cluster", "R-MAT scale 14 ef 16 (0.57,0.19,0.19,0.05)"),
     "grid4096": ("grid4096_batch128", "4096x4096 4-neighbour grid, 5% of edges deleted"),
     "chunglu25": ("chunglu25_batch64", "Chung-Lu beta 2.1, n 2^25, average degree 30"),
 }
@@ -76,20 +77,152 @@ def load_traffic(kind: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
+def golden_pairs(n, m):
+    """Oracle answers (tests/golden/serve_rmat22_pairs.txt, written by the
+    golden script from the oracle) of the first queries of the serving stream,
+    if they were made for this graph."""
+    path = os.path.join(ROOT, "tests", "golden", "serve_rmat22_pairs.txt")
+    if not os.path.exists(path):
+        return None
+    meta, ans = {}, []
+    with open(path) as f:
+        for ln in f:
+            if ln.startswith("# n="):
+                meta = dict(kv.split("=") for kv in ln[2:].split())
+            elif ln.startswith("stream "):
+                ans.append(int(ln.split()[3]))
+    if int(meta.get("n", -1)) != n or int(meta.get("m", -1)) != m:
+        return None
+    return np.array(ans, dtype=np.uint32)
+
+
+def median_call_ms(fn, reps, warm=2):
+    import torch
+    st = torch.cuda.current_stream()
+    for _ in range(warm):
+        fn(st)
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        fn(st)
+        b.record(st)
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    return float(np.median(times))
+
+
+def diameter_table(P, torch, rp, col, rp_d, col_d, m):
+    """Time of C-BFS in the paper's own encoding for clusters of diameter
+    d = 2..6 (each: the highest-degree free vertex and the 63 highest-degree
+    free vertices within floor(d/2) hops, Section 4.2), relative to d = 2."""
+    rows = []
+    for d in range(2, 7):
+        cp, src = P.select_landmarks(rp, col, 64, 64, d)
+        one = np.array([0, cp[1]], np.int32)
+        out1 = P.run_batch(rp_d, col_d, one, src[: cp[1]], d, encoding=P.CBFS_ENCODE_MIN)
+        t1 = median_call_ms(lambda st: P.run_batch(rp_d, col_d, one, src[: cp[1]], d, out=out1, stream=st,
+                                                   encoding=P.CBFS_ENCODE_MIN), 7)
+        st1 = out1[2].cpu().numpy()
+        outb = P.run_batch(rp_d, col_d, cp, src, d, encoding=P.CBFS_ENCODE_MIN)
+        tb = median_call_ms(lambda st: P.run_batch(rp_d, col_d, cp, src, d, out=outb, stream=st,
+                                                   encoding=P.CBFS_ENCODE_MIN), 3, warm=1)
+        ok = bool((st1 == 0).all() and (outb[2].cpu().numpy() == 0).all())
+        ksum = int(cp[-1])
+        rows.append({"d": d, "one_cluster_ms": round(t1, 3), "batch_clusters": int(cp.size - 1), "batch_ms": round(tb, 2),
+                     "batch_source_gteps": round(ksum * m / (tb * 1e-3) / 1e9, 1), "status_ok": ok})
+        del outb, out1
+    base1, baseb = rows[0]["one_cluster_ms"], rows[0]["batch_ms"]
+    for r in rows:
+        r["one_cluster_rel"] = round(r["one_cluster_ms"] / base1, 3)
+        r["batch_rel"] = round(r["batch_ms"] / baseb, 3)
+    return rows
+
+
+def ll_distortion(P, torch, rp, col, rp_d, col_d, pairs=512, seed=91):
+    """Landmark labeling as Section 4.2 builds it (clusters of 64 selected by
+    degree with marking, d = 2, star labels with offsets -1 and 0) for several
+    label counts; distortion of the query answer against exact distances from
+    a GPU batch of single-source searches (radius 0)."""
+    import synth
+    n = rp.size - 1
+    qs, qt = synth.query_pairs(n, pairs, seed)
+    one = np.arange(pairs + 1, dtype=np.int32)
+    ex_d, _, ex_st = P.run_batch(rp_d, col_d, one, qs, 0)
+    exact = ex_d.cpu().numpy().view(np.uint32)[np.arange(pairs), qt].astype(np.int64)
+    del ex_d
+    assert (ex_st.cpu().numpy() == 0).all()
+    qs_d, qt_d = torch.from_numpy(qs).to(rp_d.device), torch.from_numpy(qt).to(rp_d.device)
+    out = []
+    for r in (16, 64, 128):
+        cp, src = P.select_landmarks(rp, col, r, 64, 2)
+        dist, masks, st = P.run_batch(rp_d, col_d, cp, src, 1)
+        dvm, mvm = P.labels_pack(dist, masks, 1)
+        ans = P.query_batch(dvm, mvm, 1, qs_d, qt_d).cpu().numpy().view(np.uint32).astype(np.int64)
+        pos = exact > 0
+        ratio = ans[pos] / exact[pos]
+        out.append({"clusters": int(cp.size - 1), "landmarks": int(cp[-1]), "pairs": int(pos.sum()),
+                    "label_bytes_per_vertex": int((dvm.numel() * 4 + mvm.numel() * 8) // n),
+                    "mean_distortion": round(float(ratio.mean()), 4), "max_distortion": round(float(ratio.max()), 3),
+                    "exact_fraction": round(float((ans[pos] == exact[pos]).mean()), 4),
+                    "bound_holds": bool((ans >= exact).all())})
+        del dist, masks, dvm, mvm
+    return out
+
+
+def rmat14_latency(P, torch, dev):
+    """The one-cluster R-MAT scale-14 workload: time of one cbfs_run_batch
+    (median of 20 after 3 warm-ups), graph and outputs resident."""
+    from synth import configs
+    cfg = configs.WORKLOADS["rmat14"]
+    n_in, src, dst = configs.raw_graph("rmat14")
+    rp, col, _ = P.build_csr(n_in, src, dst)
+    cp, s = P.select_clusters(rp, col, P.top_degree(rp, 1), cfg["k"], cfg["hops"])
+    rp_d, col_d = torch.from_numpy(rp).to(dev), torch.from_numpy(col).to(dev)
+    out = P.run_batch(rp_d, col_d, cp, s, cfg["R"])
+    ws = torch.empty(P.run_batch_workspace_size(rp_d, col_d, cp, s, cfg["R"]), dtype=torch.uint8, device=dev)
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        P.run_batch(rp_d, col_d, cp, s, cfg["R"], out=out, workspace=ws, stream=st)
+    times = []
+    for _ in range(20):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        P.run_batch(rp_d, col_d, cp, s, cfg["R"], out=out, workspace=ws, stream=st)
+        b.record(st)
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    ms = float(np.median(times))
+    k = int(cp[-1])
+    return {"workload": "rmat14_one_cluster", "n": int(rp.size - 1), "m_arcs": int(col.size), "sources": k,
+            "median_ms": round(ms, 4), "source_gteps": round(k * col.size / (ms * 1e-3) / 1e9, 2),
+            "stats": P.last_run_stats()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", type=int, default=0, help="0 auto, 1 host loop, 2 persistent")
     ap.add_argument("--group-words", type=int, default=0)
     ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--alpha", type=float, default=0.0, help="push/pull threshold (0 = library default)")
+    ap.add_argument("--gamma", type=float, default=0.0, help="wave-form threshold (0 = library default)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-clusters", type=int, default=6, help="clusters in the CPU oracle sample")
     ap.add_argument("--no-query", action="store_true")
-    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "grid4096", "chunglu25"],
+    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "grid4096", "chunglu25", "rmat14"],
                     help="batch workload (the default is the headline one)")
+    ap.add_argument("--no-rmat14", action="store_true", help="skip the one-cluster R-MAT 14 latency figure")
+    ap.add_argument("--serve-queries", type=int, default=1_000_000, help="queries served per offered rate")
+    ap.add_argument("--diameters", action="store_true",
+                    help="also time clusters of diameter d = 2..6 in the paper's own encoding <S_v[0..d], Delta_v> "
+                         "(landmark selection of Section 4.2), one cluster per call and a 64-cluster batch")
+    ap.add_argument("--ll", action="store_true",
+                    help="also measure landmark-labeling distortion (clusters selected as in Section 4.2) against "
+                         "exact distances computed on the GPU")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the launch knobs on the first 16 clusters before timing (untimed)")
     ap.add_argument("--copy-only", type=int, default=0,
@@ -155,7 +288,8 @@ def main():
     torch.cuda.set_device(dev)
     rp_d = torch.from_numpy(rp).to(dev)
     col_d = torch.from_numpy(col).to(dev)
-    tuning = P.Tuning(mode=args.mode, group_words=args.group_words, concurrent_groups=args.slots)
+    tuning = P.Tuning(mode=args.mode, group_words=args.group_words, concurrent_groups=args.slots,
+                      alpha=args.alpha, gamma=args.gamma)
     tuned = None
     if args.tune:
         t0 = time.time()
@@ -179,15 +313,20 @@ def main():
     stream = torch.cuda.current_stream()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     wall0 = time.time()
     ev0.record(stream)
-    for _ in range(args.steps):
+    for k in range(args.steps):
+        marks[k].record(stream)
         P.run_batch(rp_d, col_d, cptr, sources, R, tuning, out=out, workspace=ws, stream=stream)
+    marks[args.steps].record(stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.time() - wall0
     step_ms = ev0.elapsed_time(ev1) / args.steps
+    per_step = [marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps)]
+    median_ms = float(np.median(per_step))
     # one more step with every kernel launch bracketed by HIP events on the
     # library's stream, for the per-kernel attribution of the roofline
     P.profile_enable(True)
@@ -259,6 +398,14 @@ def main():
                "kind": "oracle", "sample": f"first {nc} clusters ({int(cps[-1])} sources, one BFS each) "
                                            f"of the same workload, {cpu_s:.1f} s",
                "gpu_matches_sample": same}
+        # the same oracle on one thread, over the first 24 sources of the first cluster
+        k1 = int(min(24, cptr[1]))
+        t = time.time()
+        od1, om1, _ = oracle.cbfs(rp, col, np.array([0, k1], np.int32), sources[:k1], R=R, W=k_w, nthreads=1)
+        cpu1_s = time.time() - t
+        cpu["one_thread"] = {"value": round(k1 * m / cpu1_s / 1e9, 3), "unit": "GTEPS", "cores": 1,
+                             "sample": f"first {k1} sources of the first cluster, {cpu1_s:.1f} s"}
+        del od1, om1
         print(f"[bench] cpu: {cpu}", file=sys.stderr, flush=True)
 
     # serving: labels of the first 128 clusters (the top-128 centers) kept on
@@ -282,16 +429,33 @@ def main():
         kernel_ms = ev0.elapsed_time(ev1)
         query = {"clusters": CQ, "landmarks": int(cptr[CQ]), "label_bytes": int(dvm.numel() * 4 + mvm.numel() * 8),
                  "device_qps_1M_batch": round(qn / (kernel_ms * 1e-3), 1), "rates": []}
+        gold = golden_pairs(n, m) if CQ == 128 else None
         ex = server.GpuExecutor(dvm, mvm, R, max_batch=1 << 16, lanes=4)
-        for rate, count in ((1e5, 100_000), (1e6, 500_000), (1e7, 1_000_000)):
+        count = min(args.serve_queries, qn)
+        one_batch = ans_d[:count].cpu().numpy().view(np.uint32)
+        for rate in (1e5, 1e6, 1e7):
             arr = synth.poisson_arrivals(rate, count, int(rate))
             rep = server.serve(ex, qs[:count], qt[:count], arr)
-            same = bool(np.array_equal(rep.answers, ans_d[:count].cpu().numpy().view(np.uint32)))
+            same = bool(np.array_equal(rep.answers, one_batch))
             summ = rep.summary()
             summ.update({"offered_qps": rate, "same_as_one_batch": same})
+            if gold is not None:
+                g = min(gold.size, count)
+                summ["same_as_oracle_first"] = g if bool(np.array_equal(rep.answers[:g], gold[:g])) else -1
             query["rates"].append({k: (round(v, 2) if isinstance(v, float) else v) for k, v in summ.items()})
             print(f"[bench] serve {rate:.0e} QPS: {summ}", file=sys.stderr, flush=True)
         del dvm, mvm
+
+    dtab = diameter_table(P, torch, rp, col, rp_d, col_d, m) if args.diameters else None
+    if dtab:
+        print(f"[bench] diameters: {dtab}", file=sys.stderr, flush=True)
+    ll = ll_distortion(P, torch, rp, col, rp_d, col_d) if args.ll else None
+    if ll:
+        print(f"[bench] landmark labeling: {ll}", file=sys.stderr, flush=True)
+    r14 = None
+    if not args.no_rmat14 and args.workload == "rmat22":
+        r14 = rmat14_latency(P, torch, dev)
+        print(f"[bench] rmat14: {r14}", file=sys.stderr, flush=True)
 
     line = {
         "metric": METRIC, "value": round(gteps, 2), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
@@ -302,8 +466,15 @@ def main():
                    "group_words": stats["group_words"], "mode": stats["mode"], "slots": stats["slots"],
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "query": query, "autotune": tuned,
-        "run_stats": stats,
+        "run_stats": stats, "median_ms_per_step": round(median_ms, 3),
+        "per_step_ms": [round(x, 3) for x in per_step], "rmat14": r14,
     }
+    if dtab:
+        line["diameters"] = dtab
+    if ll:
+        line["landmark_labeling"] = ll
+    if stats["mode"] == 2 or args.workload == "grid4096":
+        line["levels_per_s"] = round(stats["rounds"] / (step_ms * 1e-3), 1)
     print(json.dumps(line), flush=True)
 
 

@@ -29,7 +29,7 @@ import subprocess
 
 import numpy as np
 
-from .csr import clean_csr_numpy, top_degree, cluster_around, build_clusters  # noqa: F401
+from .csr import clean_csr_numpy, top_degree, cluster_around, build_clusters, select_landmarks  # noqa: F401
 from .csr import FLAGS_ALL
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

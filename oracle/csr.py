@@ -114,3 +114,47 @@ def build_clusters(row_ptr, col, centers, k: int, hops: int):
     cluster_ptr[1:] = np.cumsum([p.size for p in parts])
     sources = np.concatenate(parts) if parts else np.zeros(0, np.int32)
     return cluster_ptr, sources.astype(np.int32)
+
+
+def select_landmarks(row_ptr, col, num_clusters: int, k: int, diameter: int):
+    """Section 4.2, "Selecting Landmarks in Clusters", written out: the unmarked
+    vertex of highest degree (ties: lower id) is a center; among its unmarked
+    vertices within floor(d/2) hops, the k-1 of highest degree (same ties) join
+    it; every chosen vertex is marked.  Repeated num_clusters times or until
+    every vertex is marked.  Each cluster: center, then members by descending
+    degree.  Returns (cluster_ptr, sources)."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col)
+    n = row_ptr.size - 1
+    deg = np.diff(row_ptr)
+    order = np.lexsort((np.arange(n), -deg))
+    marked = np.zeros(n, dtype=bool)
+    hops = diameter // 2
+    parts = []
+    for c in order:
+        if len(parts) == num_clusters:
+            break
+        if marked[c]:
+            continue
+        # BFS ball of radius hops around c (through marked vertices too)
+        seen = {int(c)}
+        layer = [int(c)]
+        ball = []
+        for _ in range(hops):
+            nxt = []
+            for u in layer:
+                for v in col[row_ptr[u]:row_ptr[u + 1]]:
+                    v = int(v)
+                    if v not in seen:
+                        seen.add(v)
+                        nxt.append(v)
+            ball.extend(v for v in nxt if not marked[v])
+            layer = nxt
+        ball.sort(key=lambda v: (-int(deg[v]), v))
+        cl = [int(c)] + ball[: k - 1]
+        marked[cl] = True
+        parts.append(np.array(cl, dtype=np.int32))
+    cluster_ptr = np.zeros(len(parts) + 1, dtype=np.int32)
+    cluster_ptr[1:] = np.cumsum([p.size for p in parts])
+    sources = np.concatenate(parts) if parts else np.zeros(0, np.int32)
+    return cluster_ptr, sources.astype(np.int32)

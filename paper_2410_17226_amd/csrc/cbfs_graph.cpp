@@ -237,3 +237,72 @@ extern "C" cbfs_status cbfs_select_clusters(int64_t n, const int32_t *row_ptr, c
         return cbfs::fail(CBFS_E_NOMEM, "cbfs_select_clusters: out of host memory");
     }
 }
+
+// Landmark clusters as the paper builds them (Section 4.2, "Selecting
+// Landmarks in Clusters"): repeatedly take the unmarked vertex of highest
+// degree as a center; among its unmarked vertices within floor(d/2) hops take
+// the k-1 of highest degree; mark the whole cluster so that no later cluster
+// reuses a vertex.  Degree ties go to the lower id.  Sources are listed center
+// first, then in selection order (degree descending).  Stops early when every
+// vertex is marked.
+extern "C" cbfs_status cbfs_select_landmarks(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                                             int32_t num_clusters, int32_t k, int32_t diameter,
+                                             int32_t *cluster_ptr, int32_t *sources, int64_t sources_capacity,
+                                             int32_t *num_selected)
+{
+    if (n <= 0 || !row_ptr || !col || num_clusters < 0 || diameter < 0 || !cluster_ptr || !sources ||
+        !num_selected)
+        return cbfs::fail(CBFS_E_ARG, "cbfs_select_landmarks: bad argument");
+    if (k < 1 || k > CBFS_MAX_SOURCES)
+        return cbfs::fail(CBFS_E_TOO_MANY_SOURCES, "cbfs_select_landmarks: k outside 1..256");
+    try {
+        // vertices by degree descending, ties by ascending id
+        std::vector<int32_t> order(n);
+        for (int64_t v = 0; v < n; v++) order[v] = (int32_t)v;
+        auto deg = [&](int32_t v) { return row_ptr[v + 1] - row_ptr[v]; };
+        auto before = [&](int32_t a, int32_t b) { return deg(a) != deg(b) ? deg(a) > deg(b) : a < b; };
+        std::stable_sort(order.begin(), order.end(), before);
+        std::vector<char> marked(n, 0);
+        std::vector<int32_t> stamp(n, -1), frontier, next, ball;
+        const int32_t hops = diameter / 2;
+        int64_t pos = 0, scan = 0;
+        int32_t made = 0;
+        cluster_ptr[0] = 0;
+        while (made < num_clusters) {
+            while (scan < n && marked[order[scan]]) scan++;
+            if (scan == n) break;
+            const int32_t c = order[scan];
+            ball.clear();
+            frontier.assign(1, c);
+            stamp[c] = made;
+            for (int32_t h = 0; h < hops && !frontier.empty(); h++) {
+                next.clear();
+                for (int32_t u : frontier)
+                    for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; e++) {
+                        const int32_t w = col[e];
+                        if (stamp[w] != made) {
+                            stamp[w] = made;
+                            next.push_back(w);
+                            if (!marked[w]) ball.push_back(w);
+                        }
+                    }
+                frontier.swap(next);
+            }
+            const size_t take = std::min<size_t>(ball.size(), size_t(k - 1));
+            std::partial_sort(ball.begin(), ball.begin() + take, ball.end(), before);
+            if (pos + 1 + int64_t(take) > sources_capacity)
+                return cbfs::fail(CBFS_E_WORKSPACE, "cbfs_select_landmarks: sources capacity too small");
+            sources[pos++] = c;
+            marked[c] = 1;
+            for (size_t i = 0; i < take; i++) {
+                sources[pos++] = ball[i];
+                marked[ball[i]] = 1;
+            }
+            cluster_ptr[++made] = int32_t(pos);
+        }
+        *num_selected = made;
+        return CBFS_OK;
+    } catch (const std::bad_alloc &) {
+        return cbfs::fail(CBFS_E_NOMEM, "cbfs_select_landmarks: out of host memory");
+    }
+}

@@ -55,3 +55,57 @@ def test_query_batch_any_radius_matches_landmark_oracle(R, seed):
     # the labels' own query evaluated by the oracle from the oracle's encode agrees too
     od, om, ost = oracle.cbfs(orp, ocol, ocp, osrc, R=R)
     assert np.array_equal(oracle.query_labels(od, om, qs, qt), want)
+
+
+@pytest.mark.parametrize("dd", [2, 4])
+def test_landmark_labeling_as_the_paper_builds_it(dd):
+    """Section 4.2's index: clusters selected by degree with marking within
+    floor(d/2) hops (library and oracle selections agree), C-BFS labels with
+    R = floor(d/2) built by the HIP path, queries equal to the brute force
+    over the same landmarks, never below the exact distance, and exact when
+    an endpoint is a landmark."""
+    torch = _torch()
+    import paper_2410_17226_amd as P
+    n, s, d = synth.rmat_edges(12, 16, seed=70 + dd)
+    rp, col, _ = P.build_csr(n, s, d)
+    orp, ocol, _ = oracle.clean_csr(n, s, d)
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+    cp, src = P.select_landmarks(rp, col, 24, 64, dd)
+    ocp, osrc = oracle.select_landmarks(orp, ocol, 24, 64, dd)
+    assert np.array_equal(cp, ocp) and np.array_equal(src, osrc)
+    R = dd // 2
+    nv = rp.size - 1
+    print(f"[ll] d={dd} n={nv} clusters={cp.size - 1} landmarks={src.size}", flush=True)
+    rp_d, col_d = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    dist, masks, st = P.run_batch(rp_d, col_d, cp, src, R)
+    assert (st.cpu().numpy() == 0).all()
+    dvm, mvm = P.labels_pack(dist, masks, R)
+    qs, qt = synth.query_pairs(nv, 3000, 7 + dd)
+    qs[:30] = src[:30]
+    got = P.query_batch(dvm, mvm, R, torch.from_numpy(qs).cuda(), torch.from_numpy(qt).cuda())
+    got = got.cpu().numpy().view(np.uint32)
+    want = oracle.query_landmarks(orp, ocol, ocp, osrc, qs, qt)
+    assert np.array_equal(got, want)
+    exact = oracle.pair_distances(orp, ocol, qs, qt)
+    assert (got.astype(np.int64) >= exact.astype(np.int64)).all()
+    assert np.array_equal(got[:30], exact[:30])
+
+
+@pytest.mark.parametrize("dd", [2, 3, 4, 5, 6])
+def test_min_relative_on_landmark_clusters_of_each_diameter(dd):
+    """Clusters of diameter d = 2..6 from the paper's selection, encoded in
+    the paper's own form <S_v[0..d], Delta_v>, bit for bit against the oracle."""
+    torch = _torch()
+    import paper_2410_17226_amd as P
+    n, s, d = synth.rmat_edges(12, 16, seed=80)
+    rp, col, _ = P.build_csr(n, s, d)
+    cp, src = P.select_landmarks(rp, col, 12, 64, dd)
+    rp_d, col_d = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    print(f"[minrel] d={dd} clusters={cp.size - 1}", flush=True)
+    for tun in (None, P.Tuning(force_pull=1), P.Tuning(alpha=-1.0)):
+        dist, masks, st = P.run_batch(rp_d, col_d, cp, src, dd, tun, encoding=P.CBFS_ENCODE_MIN)
+        od, om, ost = oracle.cbfs_min(rp, col, cp, src, dd)
+        assert (ost == 0).all()
+        assert np.array_equal(st.cpu().numpy(), ost)
+        assert np.array_equal(dist.cpu().numpy().view(np.uint32), od)
+        assert np.array_equal(masks.cpu().numpy().view(np.uint64), om)

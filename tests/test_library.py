@@ -77,6 +77,18 @@ def test_selection_matches_oracle():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+def test_landmark_selection_matches_oracle():
+    """The library's Section 4.2 selection (degree priority, floor(d/2) hops,
+    marking) equals the oracle side's own implementation."""
+    for seed in range(3):
+        n, s, d = synth.rmat_edges(11, 16, seed=seed)
+        rp, col, _ = P.build_csr(n, s, d)
+        for C, k, dd in ((20, 64, 2), (50, 16, 4), (3000, 8, 3), (30, 256, 2), (10, 1, 6)):
+            a = P.select_landmarks(rp, col, C, k, dd)
+            b = oracle.select_landmarks(rp, col, C, k, dd)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (seed, C, k, dd)
+
+
 def test_select_clusters_errors():
     rp = np.array([0, 1, 2], np.int32)
     col = np.array([1, 0], np.int32)

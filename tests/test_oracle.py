@@ -642,3 +642,34 @@ def test_selection_rules():
     assert list(cl) == [55, 35, 44, 45, 46, 53, 54, 56, 57, 64, 65, 66, 75]
     cl = oracle.cluster_around(rp, col, 55, 5, 2)
     assert list(cl) == [55, 35, 44, 45, 46]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_landmark_selection_rule(seed):
+    """Section 4.2's selection, checked from its statement on all-pairs
+    distances: no vertex in two clusters; each center is the unmarked vertex
+    of highest degree (lower id on ties) when it is chosen; every member lies
+    within floor(d/2) hops of its center (so the cluster's diameter is at most
+    d); the members are the highest-degree unmarked vertices of that ball."""
+    n, s, d = synth.rmat_edges(8, 8, seed=seed + 60)
+    rp, col, _ = oracle.clean_csr(n, s, d)
+    D = apsp(rp, col)
+    deg = np.diff(rp)
+    nv = rp.size - 1
+    for k, dd in ((8, 2), (5, 4), (12, 3)):
+        cp, src = oracle.select_landmarks(rp, col, 1000, k, dd)
+        assert np.unique(src).size == src.size
+        marked = np.zeros(nv, bool)
+        for c in range(cp.size - 1):
+            cl = src[cp[c]:cp[c + 1]]
+            center = cl[0]
+            free = np.nonzero(~marked)[0]
+            best = free[np.lexsort((free, -deg[free]))[0]]
+            assert center == best
+            ball = [v for v in free if v != center and 0 <= D[center, v] <= dd // 2]
+            ball.sort(key=lambda v: (-deg[v], v))
+            assert list(cl[1:]) == ball[: k - 1]
+            sub = D[np.ix_(cl, cl)]
+            assert sub.max() <= dd
+            marked[cl] = True
+        assert marked.all()  # 1000 clusters exhaust the graph
