@@ -202,7 +202,9 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
     }
     p.groups = (p.C + p.per_group - 1) / p.per_group;
     if (p.mode == CBFS_MODE_PERSISTENT) {
-        int32_t sl = want_slots ? want_slots : (sparse ? 32 : 1);
+        // dense graphs: one group per die at least (the persistent kernel
+        // deals slots to the dies, and a die without a slot sits idle)
+        int32_t sl = want_slots ? want_slots : (sparse ? 32 : DIES);
         p.slots = std::max(1, std::min(sl, p.groups));
     } else {
         p.slots = 1;
