@@ -15,6 +15,8 @@ product package, and the product package never imports it.
                          Algorithm "Framework of Landmark Labeling", Query).
 * ``pair_distances``  -- exact delta(s, t) per pair (one BFS from s), the
                          ground truth landmark answers bound from above.
+* ``local_search``    -- the query path's bidirectional local search
+                         (Appendix B), tau vertices from each endpoint.
 * ``query_labels``    -- the same query from encoded labels by the lowest
                          non-empty intersection (Section 4.2).
 * ``certificate``     -- BFS-distance certificate of any encoded output.
@@ -71,6 +73,8 @@ def _load():
         lib.oracle_query_landmarks.restype = ctypes.c_int
         lib.oracle_pair_distances.argtypes = [i64, P, P, i64, P, P, P, i32]
         lib.oracle_pair_distances.restype = ctypes.c_int
+        lib.oracle_local_search.argtypes = [i64, P, P, i64, P, P, i32, P, i32]
+        lib.oracle_local_search.restype = ctypes.c_int
         lib.oracle_query_labels.argtypes = [i64, i32, i32, P, P, i64, P, P, P]
         lib.oracle_query_labels.restype = ctypes.c_int
         lib.oracle_certificate.argtypes = [i64, P, P, i32, P, i32, i32, P, P, i32]
@@ -183,6 +187,20 @@ def pair_distances(row_ptr, col, qs, qt, nthreads: int = 0) -> np.ndarray:
                                        int(nthreads))
     if rc != 0:
         raise ValueError(f"oracle_pair_distances failed: {rc}")
+    return out
+
+
+def local_search(row_ptr, col, qs, qt, tau: int, nthreads: int = 0) -> np.ndarray:
+    """Bidirectional local search (Appendix B): min over the vertices found by
+    both tau-bounded BFSs of d(s,x) + d(t,x) (uint32, UINT32_MAX if none)."""
+    row_ptr, col, n = _csr(row_ptr, col)
+    qs = np.ascontiguousarray(qs, dtype=np.int32)
+    qt = np.ascontiguousarray(qt, dtype=np.int32)
+    out = np.empty(qs.size, dtype=np.uint32)
+    rc = _load().oracle_local_search(n, _p(row_ptr), _p(col), qs.size, _p(qs), _p(qt), int(tau), _p(out),
+                                     int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_local_search failed: {rc}")
     return out
 
 

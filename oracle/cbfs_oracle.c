@@ -469,6 +469,84 @@ int oracle_pair_distances(int64_t n, const int32_t *row_ptr, const int32_t *col,
     return OR_OK;
 }
 
+/* Bidirectional local search of the query path (Appendix B, "Applying
+ * Bi-Directional Search in the Queries"): from each endpoint, the first tau
+ * vertices a plain FIFO BFS discovers (the root first, then each dequeued
+ * vertex's neighbours in row order, a vertex counted when it is first seen),
+ * each with its exact distance; the answer is the minimum over the vertices
+ * both searches discovered of d(s,x) + d(t,x), UINT32_MAX if they share none.
+ * It is combined with the landmark answer by a minimum (the common vertices
+ * act as landmarks found on the fly). */
+static void local_bfs(const int32_t *row_ptr, const int32_t *col, int32_t root, int32_t tau,
+                      int32_t *dist, int32_t *list, int32_t *count)
+{
+    int32_t head = 0, cnt = 0;
+    list[cnt++] = root;
+    dist[root] = 0;
+    while (head < cnt && cnt < tau) {
+        const int32_t u = list[head++];
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1] && cnt < tau; e++) {
+            const int32_t v = col[e];
+            if (dist[v] == UNREACHED) {
+                dist[v] = dist[u] + 1;
+                list[cnt++] = v;
+            }
+        }
+    }
+    *count = cnt;
+}
+
+typedef struct {
+    int64_t n;
+    const int32_t *row_ptr, *col, *qs, *qt;
+    int32_t tau;
+    uint32_t *out;
+    int32_t *bufs;
+} local_ctx;
+
+static void local_body(int64_t lo, int64_t hi, int tid, void *p)
+{
+    local_ctx *c = (local_ctx *)p;
+    const int64_t n = c->n;
+    int32_t *ds = c->bufs + (size_t)tid * 2 * ((size_t)n + (size_t)c->tau);
+    int32_t *dt = ds + n;
+    int32_t *ls = dt + n;
+    int32_t *lt = ls + c->tau;
+    for (int64_t v = 0; v < n; v++) ds[v] = dt[v] = UNREACHED;
+    for (int64_t j = lo; j < hi; j++) {
+        int32_t cs = 0, ct = 0;
+        local_bfs(c->row_ptr, c->col, c->qs[j], c->tau, ds, ls, &cs);
+        local_bfs(c->row_ptr, c->col, c->qt[j], c->tau, dt, lt, &ct);
+        uint32_t best = UINT32_MAX;
+        for (int32_t k = 0; k < cs; k++) {
+            const int32_t x = ls[k];
+            if (dt[x] != UNREACHED) {
+                const uint32_t cand = (uint32_t)(ds[x] + dt[x]);
+                if (cand < best) best = cand;
+            }
+        }
+        c->out[j] = best;
+        for (int32_t k = 0; k < cs; k++) ds[ls[k]] = UNREACHED;  /* reset only what was touched */
+        for (int32_t k = 0; k < ct; k++) dt[lt[k]] = UNREACHED;
+    }
+}
+
+int oracle_local_search(int64_t n, const int32_t *row_ptr, const int32_t *col, int64_t q,
+                        const int32_t *qs, const int32_t *qt, int32_t tau, uint32_t *out, int32_t nthreads)
+{
+    if (n <= 0 || q < 0 || tau < 1) return OR_E_ARG;
+    for (int64_t j = 0; j < q; j++)
+        if (qs[j] < 0 || qs[j] >= n || qt[j] < 0 || qt[j] >= n) return OR_E_ARG;
+    int nt = nthreads_or_default(nthreads);
+    if (nt > q) nt = q > 0 ? (int)q : 1;
+    int32_t *bufs = (int32_t *)malloc(sizeof(int32_t) * 2 * ((size_t)n + (size_t)tau) * (size_t)nt);
+    if (!bufs) return OR_E_NOMEM;
+    local_ctx c = {n, row_ptr, col, qs, qt, tau, out, bufs};
+    parallel_for(q, 64, nt, local_body, &c);
+    free(bufs);
+    return OR_OK;
+}
+
 /* The same query from encoded labels (dist[C][n], masks[C][2R+1][n][1], k <= 64):
  * per cluster, scan offset pairs (a, b) in increasing order of a + b and stop at
  * the first non-empty intersection mask[a][s] & mask[b][t]; the candidate is

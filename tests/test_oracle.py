@@ -8,6 +8,8 @@
 * invariants from the Fact / Corollary of Section 3.1;
 * the two query oracles against each other, against true distances (one-sided
   error, Section 4.2) and against the fixture;
+* the bidirectional local search (Appendix B) against scipy's BFS order and
+  all-pairs distances, the path closed form, full coverage and tau = 1;
 * the BFS certificate against planted mistakes;
 * the oracle's C cleanup against its numpy/scipy form.
 """
@@ -16,7 +18,7 @@ import os
 import numpy as np
 import pytest
 import scipy.sparse as sp
-from scipy.sparse.csgraph import shortest_path
+from scipy.sparse.csgraph import breadth_first_order, shortest_path
 
 import oracle
 import synth
@@ -480,6 +482,78 @@ def test_pair_distances_path_closed_form():
     qs, qt = np.meshgrid(np.arange(n, dtype=np.int32), np.arange(n, dtype=np.int32))
     got = oracle.pair_distances(rp, col, qs.ravel(), qt.ravel())
     assert np.array_equal(got.astype(np.int64), np.abs(qs.ravel() - qt.ravel()).astype(np.int64))
+
+
+def local_from_library(rp, col, D, s, t, tau):
+    """The local search answer from scipy's BFS discovery order (FIFO, row
+    order) and an all-pairs distance matrix."""
+    n = rp.size - 1
+    A = sp.csr_matrix((np.ones(col.size), col, rp), shape=(n, n))
+    a = breadth_first_order(A, int(s), directed=True, return_predecessors=False)[:tau]
+    b = set(breadth_first_order(A, int(t), directed=True, return_predecessors=False)[:tau].tolist())
+    c = [int(D[s, x] + D[t, x]) for x in a if int(x) in b]
+    return min(c) if c else int(U32MAX)
+
+
+@pytest.mark.parametrize("name,g", small_graphs()[::3] + [small_graphs()[-1]])
+def test_local_search_matches_library_bfs_order(name, g):
+    n, s, d = g
+    rp, col, _ = oracle.clean_csr(n, s, d, flags=7)
+    D = apsp(rp, col)
+    nv = rp.size - 1
+    qs, qt = synth.query_pairs(nv, 60, 11)
+    qs[:3] = qt[:3]
+    for tau in (1, 2, 3, 7, 20, nv):
+        got = oracle.local_search(rp, col, qs, qt, tau, nthreads=2)
+        want = [local_from_library(rp, col, D, a, b, tau) for a, b in zip(qs, qt)]
+        assert got.tolist() == want, tau
+        ok = D[qs, qt] >= 0
+        assert np.all(got[ok].astype(np.int64) >= D[qs, qt][ok])  # never below the true distance
+        assert np.all(got[~ok] == U32MAX)
+
+
+def test_local_search_row_order_matters():
+    """The discovery order follows each row's stored order (not sorted ids)."""
+    rp = np.array([0, 3, 4, 5, 6, 7], np.int32)   # row 0 stored as 3, 1, 2; 1, 2, 3 and 4 point to 0
+    col = np.array([3, 1, 2, 0, 0, 0, 0], np.int32)
+    D = apsp(rp, col)
+    for t in range(5):
+        for tau in (1, 2, 3, 4):
+            assert oracle.local_search(rp, col, [0], [t], tau)[0] == local_from_library(rp, col, D, 0, t, tau)
+    # tau = 2 from 0 finds {0, 3} (first stored neighbour), not {0, 1}
+    assert oracle.local_search(rp, col, [0], [3], 2)[0] == 1
+    assert oracle.local_search(rp, col, [0], [1], 2)[0] == 1  # 1 finds 0 itself
+
+
+def test_local_search_path_closed_form():
+    """On a path with sorted rows, a search of tau vertices from an interior
+    s covers s - ceil((tau-1)/2) .. s + floor((tau-1)/2); two searches meet iff
+    the intervals overlap, and then the answer is exact."""
+    n = 200
+    rp, col = csr_of(n, [(i, i + 1) for i in range(n - 1)])
+    for tau in (1, 2, 3, 4, 9, 16):
+        lo_r, hi_r = (tau - 1 + 1) // 2, (tau - 1) // 2
+        for s in range(60, 80):
+            for t in range(s, s + 40):
+                want = t - s if s + hi_r >= t - lo_r else int(U32MAX)
+                assert oracle.local_search(rp, col, [s], [t], tau)[0] == want, (tau, s, t)
+
+
+def test_local_search_full_coverage_is_exact():
+    """tau >= n: both searches cover their components, so the answer is the
+    exact distance (none across components)."""
+    n, s, d = synth.random_graph(90, 0.02, 5)
+    rp, col, _ = oracle.clean_csr(n, s, d, flags=7)
+    D = apsp(rp, col)
+    nv = rp.size - 1
+    qs, qt = synth.query_pairs(nv, 400, 2)
+    got = oracle.local_search(rp, col, qs, qt, nv)
+    want = D[qs, qt]
+    assert np.array_equal(got[want >= 0].astype(np.int64), want[want >= 0])
+    assert (got[want < 0] == U32MAX).all()
+    # tau = 1: only s == t meets
+    one = oracle.local_search(rp, col, qs, qt, 1)
+    assert np.array_equal(one == 0, qs == qt) and np.all(one[qs != qt] == U32MAX)
 
 
 def test_query_labels_radius2_matches_bruteforce():
