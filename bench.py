@@ -139,11 +139,13 @@ def diameter_table(P, torch, rp, col, rp_d, col_d, m):
     return rows
 
 
-def ll_distortion(P, torch, rp, col, rp_d, col_d, pairs=512, seed=91):
+def ll_distortion(P, torch, rp, col, rp_d, col_d, pairs=512, seed=91, local_taus=()):
     """Landmark labeling as Section 4.2 builds it (clusters of 64 selected by
     degree with marking, d = 2, star labels with offsets -1 and 0) for several
     label counts; distortion of the query answer against exact distances from
-    a GPU batch of single-source searches (radius 0)."""
+    a GPU batch of single-source searches (radius 0).  With ``local_taus``,
+    the 128-cluster labels are also combined with the bidirectional local
+    search of Appendix B for each tau."""
     import synth
     n = rp.size - 1
     qs, qt = synth.query_pairs(n, pairs, seed)
@@ -161,13 +163,58 @@ def ll_distortion(P, torch, rp, col, rp_d, col_d, pairs=512, seed=91):
         ans = P.query_batch(dvm, mvm, 1, qs_d, qt_d).cpu().numpy().view(np.uint32).astype(np.int64)
         pos = exact > 0
         ratio = ans[pos] / exact[pos]
-        out.append({"clusters": int(cp.size - 1), "landmarks": int(cp[-1]), "pairs": int(pos.sum()),
-                    "label_bytes_per_vertex": int((dvm.numel() * 4 + mvm.numel() * 8) // n),
-                    "mean_distortion": round(float(ratio.mean()), 4), "max_distortion": round(float(ratio.max()), 3),
-                    "exact_fraction": round(float((ans[pos] == exact[pos]).mean()), 4),
-                    "bound_holds": bool((ans >= exact).all())})
+        row = {"clusters": int(cp.size - 1), "landmarks": int(cp[-1]), "pairs": int(pos.sum()),
+               "label_bytes_per_vertex": int((dvm.numel() * 4 + mvm.numel() * 8) // n),
+               "mean_distortion": round(float(ratio.mean()), 4), "max_distortion": round(float(ratio.max()), 3),
+               "exact_fraction": round(float((ans[pos] == exact[pos]).mean()), 4),
+               "bound_holds": bool((ans >= exact).all())}
+        if r == 128 and local_taus:
+            row["local_search"] = local_search_table(P, torch, rp_d, col_d, dvm, mvm, qs_d, qt_d, exact, local_taus)
+        out.append(row)
         del dist, masks, dvm, mvm
     return out
+
+
+def local_search_table(P, torch, rp_d, col_d, dvm, mvm, qs_d, qt_d, exact, taus, timed_queries=1 << 17):
+    """Appendix B's trade-off: the landmark answer combined (by a minimum) with
+    a bidirectional local search of tau vertices per side.  Distortion over
+    the sampled pairs against exact distances, and the device time of
+    cbfs_query_batch + cbfs_query_local over uniform random pairs."""
+    import synth
+    n = rp_d.numel() - 1
+    ts, tt = synth.query_pairs(n, timed_queries, 93)
+    ts_d, tt_d = torch.from_numpy(ts).to(rp_d.device), torch.from_numpy(tt).to(rp_d.device)
+    out_d = torch.empty(timed_queries, dtype=torch.int32, device=rp_d.device)
+    st = torch.cuda.current_stream()
+    pos = exact > 0
+    close = pos & (exact <= 3)
+    rows = []
+    for tau in [0] + list(taus):
+        ans = P.query_batch(dvm, mvm, 1, qs_d, qt_d)
+        if tau:
+            P.query_local(rp_d, col_d, qs_d, qt_d, tau, out=ans)
+        a = ans.cpu().numpy().view(np.uint32).astype(np.int64)
+        ratio = a[pos] / exact[pos]
+        times = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            P.query_batch(dvm, mvm, 1, ts_d, tt_d, out=out_d, stream=st)
+            if tau:
+                P.query_local(rp_d, col_d, ts_d, tt_d, tau, out=out_d, stream=st)
+            e1.record(st)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        rows.append({"tau": tau, "mean_distortion": round(float(ratio.mean()), 4),
+                     "exact_fraction": round(float((a[pos] == exact[pos]).mean()), 4),
+                     "close_pairs": int(close.sum()),
+                     "close_mean_distortion": round(float((a[close] / exact[close]).mean()), 4) if close.any() else None,
+                     "bound_holds": bool((a >= exact).all()),
+                     "device_qps": round(timed_queries / (ms * 1e-3), 1),
+                     "us_per_query_amortized": round(ms * 1e3 / timed_queries, 4)})
+        print(f"[bench] local search: {rows[-1]}", file=sys.stderr, flush=True)
+    return rows
 
 
 def rmat14_latency(P, torch, dev):
@@ -223,6 +270,8 @@ def main():
     ap.add_argument("--ll", action="store_true",
                     help="also measure landmark-labeling distortion (clusters selected as in Section 4.2) against "
                          "exact distances computed on the GPU")
+    ap.add_argument("--local-taus", default="128,256,512,1024,2048",
+                    help="with --ll: local search sizes (vertices per side) combined with the 128-cluster labels")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the launch knobs on the first 16 clusters before timing (untimed)")
     ap.add_argument("--copy-only", type=int, default=0,
@@ -365,7 +414,8 @@ def main():
     # plain form: one cluster per call, same kernels and defaults
     plain = None
     if not args.no_plain:
-        one = (dist[:1], masks[:1], status[:1])
+        # outputs of their own, so the batch's labels stay intact for the query legs
+        one = (torch.empty_like(dist[:1]), torch.empty_like(masks[:1]), torch.empty_like(status[:1]))
         torch.cuda.synchronize()
         ev0.record(stream)
         for ci in range(C):
@@ -449,7 +499,8 @@ def main():
     dtab = diameter_table(P, torch, rp, col, rp_d, col_d, m) if args.diameters else None
     if dtab:
         print(f"[bench] diameters: {dtab}", file=sys.stderr, flush=True)
-    ll = ll_distortion(P, torch, rp, col, rp_d, col_d) if args.ll else None
+    taus = [int(x) for x in args.local_taus.split(",") if x.strip()]
+    ll = ll_distortion(P, torch, rp, col, rp_d, col_d, local_taus=taus) if args.ll else None
     if ll:
         print(f"[bench] landmark labeling: {ll}", file=sys.stderr, flush=True)
     r14 = None

@@ -327,7 +327,8 @@ enum {
     CBFS_KERNEL_PERSISTENT = 6,
     CBFS_KERNEL_LABELS = 7,
     CBFS_KERNEL_QUERY = 8,
-    CBFS_KERNEL_KINDS = 9
+    CBFS_KERNEL_LOCAL = 9,
+    CBFS_KERNEL_KINDS = 10
 };
 cbfs_status cbfs_profile_enable(int32_t enable);
 cbfs_status cbfs_profile_read(int64_t *launches, double *total_ms);
@@ -403,6 +404,30 @@ cbfs_status cbfs_labels_pack(const uint32_t *dist, const uint64_t *masks, int32_
                              int64_t n, int32_t radius, uint32_t *dist_vm, uint64_t *mask_vm,
                              void *stream);
 cbfs_status cbfs_query_batch(const cbfs_labels *L, int64_t q, const int32_t *s, const int32_t *t,
+                             uint32_t *ans, void *stream);
+
+/* ------------------------------------------------------------------------ *
+ * Bidirectional local search of the query path (Appendix B, "Applying
+ * Bi-Directional Search in the Queries").  From each endpoint a BFS in FIFO
+ * order (root first, then each dequeued vertex's neighbours in the order of
+ * its CSR row, a vertex counted when first seen) discovers its first tau
+ * vertices, each with its exact distance; the local answer is the lowest
+ * d(s, x) + d(t, x) over the vertices both searches discovered, none if they
+ * share none.  The common vertices act as landmarks found at query time, so
+ * the final answer is the minimum of the local and the landmark answers.
+ *
+ * cbfs_query_local: ans[j] = min(ans[j], local(s[j], t[j])) for j < q (device
+ * arrays; ans unsigned, CBFS_UNREACHED as "none"): run it after
+ * cbfs_query_batch on the same stream for the combined answer, or on ans
+ * filled with CBFS_UNREACHED for the local answer alone.  g is the graph the
+ * labels were built on (device CSR).  1 <= tau <= CBFS_LOCAL_TAU_MAX; the
+ * search state lives in on-chip memory (8 bytes per set slot, the set holding
+ * at least 1.5 (tau + 64) slots, plus 12 bytes per list entry: about 56 KiB
+ * per query at tau = 2048).  Vertex ids are not range-checked on the device.
+ * Errors: CBFS_E_ARG (null pointers, sizes, tau out of range); CBFS_E_HIP.
+ * ------------------------------------------------------------------------ */
+#define CBFS_LOCAL_TAU_MAX 2048
+cbfs_status cbfs_query_local(const cbfs_csr *g, int64_t q, const int32_t *s, const int32_t *t, int32_t tau,
                              uint32_t *ans, void *stream);
 
 #ifdef __cplusplus

@@ -25,9 +25,9 @@ SYMBOLS = [
     "cbfs_select_clusters", "cbfs_run_batch_workspace_size", "cbfs_run_batch",
     "cbfs_last_run_stats", "cbfs_profile_enable", "cbfs_profile_read",
     "cbfs_labels_pack", "cbfs_query_batch", "cbfs_autotune_workspace_size", "cbfs_autotune",
-    "cbfs_release", "cbfs_run_batch_static", "cbfs_select_landmarks",
+    "cbfs_release", "cbfs_run_batch_static", "cbfs_select_landmarks", "cbfs_query_local",
 ]
-KERNEL_KINDS = ["tiles", "init", "seed", "push", "pull", "finalize", "persistent", "labels", "query"]
+KERNEL_KINDS = ["tiles", "init", "seed", "push", "pull", "finalize", "persistent", "labels", "query", "local"]
 
 _lib = None
 
@@ -136,6 +136,8 @@ def load():
     lib.cbfs_labels_pack.restype = i32
     lib.cbfs_query_batch.argtypes = [P, i64, P, P, P, P]
     lib.cbfs_query_batch.restype = i32
+    lib.cbfs_query_local.argtypes = [P, i64, P, P, i32, P, P]
+    lib.cbfs_query_local.restype = i32
     lib.cbfs_autotune_workspace_size.argtypes = [P, P, i32]
     lib.cbfs_autotune_workspace_size.restype = sz
     lib.cbfs_autotune.argtypes = [P, P, P, i32, P, P, P, P, sz, P, P, P, i32, P]
@@ -386,6 +388,22 @@ def labels_pack(dist, masks, R: int, stream=None):
     _check(load().cbfs_labels_pack(_dptr(dist), _dptr(masks), C, n, int(R), _dptr(dist_vm), _dptr(mask_vm),
                                    _stream_ptr(stream)), "cbfs_labels_pack")
     return dist_vm, mask_vm
+
+
+LOCAL_TAU_MAX = 2048
+
+
+def query_local(row_ptr, col, s, t, tau: int, out=None, stream=None):
+    """``cbfs_query_local``: ans = min(ans, local search answer) for device int32
+    tensors s, t; without ``out`` the local answer alone (int32 tensor, uint32 bits)."""
+    torch = _torch()
+    q = s.numel()
+    if out is None:
+        out = torch.full((q,), -1, dtype=torch.int32, device=s.device)
+    g = _Csr(row_ptr.numel() - 1, col.numel(), row_ptr.data_ptr(), col.data_ptr())
+    _check(load().cbfs_query_local(ctypes.byref(g), q, _dptr(s), _dptr(t), int(tau), _dptr(out),
+                                   _stream_ptr(stream)), "cbfs_query_local")
+    return out
 
 
 def query_batch(dist_vm, mask_vm, R: int, s, t, out=None, stream=None):

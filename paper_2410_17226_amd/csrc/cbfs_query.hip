@@ -78,6 +78,209 @@ __global__ __launch_bounds__(256) void k_query(int64_t n, int32_t C, int32_t R, 
     if (lane == 0) ans[wave] = best;
 }
 
+
+// ---------------------------------------------------------------------------
+// Bidirectional local search of the query path (Appendix B, "Applying
+// Bi-Directional Search in the Queries"): from each endpoint, the first tau
+// vertices a FIFO BFS discovers (root first, then the neighbours of each
+// dequeued vertex in row order), each with its exact distance; the answer is
+// the lowest d(s,x) + d(t,x) over the vertices both searches found.
+//
+// One wave per query (a block of 64 threads), everything in LDS:
+//   keys[H], vals[H]  open-addressing set of the vertices one side has seen
+//                     (H a power of two >= 1.5 (tau + 64), so it never fills:
+//                     at most tau kept + 63 dropped keys per side);
+//   ls/lsd[tau]       s side's discovery list and distances (kept for the
+//                     intersection), lt/ltd[tau] the t side's.
+// The search scans the arcs of up to 64 queued vertices as one concatenated
+// run, 64 consecutive arcs per step, one per lane, so a step's lanes hold arcs
+// in the order the sequential search would scan them.  A neighbour seen for
+// the first time in a step may occur on several lanes; the lowest lane (the
+// earliest arc) is its discoverer, found with an LDS atomic min on its slot,
+// and discoverers take list positions by ballot rank, which reproduces the
+// sequential discovery order.  Positions >= tau are dropped (the sequential
+// search stops there); their keys stay in the set marked dropped.
+//
+// vals states: PENDING (inserted in this step, owner not decided), a lane
+// index < 64 (owner being decided), KEPT | dist, DROPPED.
+constexpr uint32_t LS_PENDING = 0xFFFFFFFFu;
+constexpr uint32_t LS_DROPPED = 0xFFFFFFFEu;
+constexpr uint32_t LS_KEPT = 0x80000000u;
+constexpr int32_t LS_EMPTY = -1;
+
+__device__ __forceinline__ uint32_t ls_hash(int32_t v, int32_t hbits)
+{
+    return ((uint32_t)v * 2654435761u) >> (32 - hbits);
+}
+
+__device__ __forceinline__ bool ls_kept(uint32_t val) { return (val >> 30) == 2u; }
+
+// Slot of v, inserting v if absent (lanes racing for one empty slot: the CAS
+// lets one key in, the others probe on unless they carry the same key).
+__device__ __forceinline__ uint32_t ls_insert(int32_t *keys, int32_t hbits, int32_t v)
+{
+    const uint32_t mask = (1u << hbits) - 1u;
+    uint32_t slot = ls_hash(v, hbits);
+    while (true) {
+        const int32_t k = keys[slot];
+        if (k == v) return slot;
+        if (k == LS_EMPTY) {
+            const int32_t old = atomicCAS(&keys[slot], LS_EMPTY, v);
+            if (old == LS_EMPTY || old == v) return slot;
+        }
+        slot = (slot + 1) & mask;
+    }
+}
+
+__device__ __forceinline__ uint32_t ls_find(const int32_t *keys, const uint32_t *vals, int32_t hbits, int32_t v)
+{
+    const uint32_t mask = (1u << hbits) - 1u;
+    uint32_t slot = ls_hash(v, hbits);
+    while (true) {
+        const int32_t k = keys[slot];
+        if (k == v) return vals[slot];
+        if (k == LS_EMPTY) return LS_DROPPED;
+        slot = (slot + 1) & mask;
+    }
+}
+
+// tau-bounded FIFO BFS from root; leaves its set in keys/vals and its
+// discovery list in list/listd; returns the list length.  Wave-uniform.
+__device__ int32_t ls_search(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, int32_t root,
+                             int32_t tau, int32_t hbits, int32_t *keys, uint32_t *vals, int32_t *list,
+                             uint16_t *listd, int32_t *pre_excl, int32_t *pre_base, int32_t *pre_dist)
+{
+    const int lane = threadIdx.x;
+    const int32_t H = 1 << hbits;
+    for (int32_t i = lane; i < H; i += 64) {
+        keys[i] = LS_EMPTY;
+        vals[i] = LS_PENDING;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        const uint32_t slot = ls_insert(keys, hbits, root);
+        vals[slot] = LS_KEPT;
+        list[0] = root;
+        listd[0] = 0;
+    }
+    __syncthreads();
+    int32_t cnt = 1, head = 0;
+    while (head < cnt && cnt < tau) {
+        const int32_t gend = head + 64 < cnt ? head + 64 : cnt;
+        const int32_t gn = gend - head;
+        int32_t deg = 0, base = 0, pd = 0;
+        if (lane < gn) {
+            const int32_t u = list[head + lane];
+            base = row_ptr[u];
+            deg = row_ptr[u + 1] - base;
+            pd = listd[head + lane];
+        }
+        int32_t incl = deg;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        const int32_t total = __shfl(incl, 63, 64);
+        pre_excl[lane] = incl - deg;
+        pre_base[lane] = base;
+        pre_dist[lane] = pd + 1;
+        __syncthreads();
+        for (int32_t a0 = 0; a0 < total && cnt < tau; a0 += 64) {
+            const int32_t g = a0 + lane;
+            bool fresh = false;
+            uint32_t slot = 0;
+            int32_t v = 0, dv = 0;
+            if (g < total) {
+                int32_t lo = 0, hi = gn - 1;  // the last queued vertex whose arcs start at or before g
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (pre_excl[mid] <= g) lo = mid;
+                    else hi = mid - 1;
+                }
+                v = col[pre_base[lo] + (g - pre_excl[lo])];
+                dv = pre_dist[lo];
+                slot = ls_insert(keys, hbits, v);
+            }
+            __syncthreads();
+            if (g < total) fresh = vals[slot] == LS_PENDING;
+            __syncthreads();
+            if (fresh) atomicMin(&vals[slot], (uint32_t)lane);
+            __syncthreads();
+            const bool first = fresh && vals[slot] == (uint32_t)lane;
+            const uint64_t won = __ballot(first);
+            __syncthreads();
+            if (first) {
+                const int32_t pos = cnt + (int32_t)__popcll(won & ((1ull << lane) - 1ull));
+                if (pos < tau) {
+                    list[pos] = v;
+                    listd[pos] = (uint16_t)dv;
+                    vals[slot] = LS_KEPT | (uint32_t)dv;
+                } else {
+                    vals[slot] = LS_DROPPED;
+                }
+            }
+            cnt += (int32_t)__popcll(won);
+            cnt = cnt < tau ? cnt : tau;
+            __syncthreads();
+        }
+        head = gend;
+    }
+    return cnt;
+}
+
+__global__ __launch_bounds__(64) void k_local_search(const int32_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col, int64_t q,
+                                                     const int32_t *qs, const int32_t *qt, int32_t tau,
+                                                     int32_t hbits, uint32_t *ans)
+{
+    extern __shared__ int32_t lds[];
+    const int32_t H = 1 << hbits;
+    int32_t *keys = lds;
+    uint32_t *vals = (uint32_t *)(keys + H);
+    int32_t *pre_excl = (int32_t *)(vals + H);
+    int32_t *pre_base = pre_excl + 64;
+    int32_t *pre_dist = pre_base + 64;
+    int32_t *ls = pre_dist + 64;
+    int32_t *lt = ls + tau;
+    uint16_t *lsd = (uint16_t *)(lt + tau);
+    uint16_t *ltd = lsd + tau;
+    const int lane = threadIdx.x;
+    for (int64_t j = blockIdx.x; j < q; j += gridDim.x) {
+        const int32_t cs = ls_search(row_ptr, col, qs[j], tau, hbits, keys, vals, ls, lsd, pre_excl, pre_base,
+                                     pre_dist);
+        ls_search(row_ptr, col, qt[j], tau, hbits, keys, vals, lt, ltd, pre_excl, pre_base, pre_dist);
+        uint32_t best = CBFS_UNREACHED;
+        for (int32_t k = lane; k < cs; k += 64) {
+            const uint32_t val = ls_find(keys, vals, hbits, ls[k]);
+            if (ls_kept(val)) {
+                const uint32_t c = (uint32_t)lsd[k] + (val & ~LS_KEPT);
+                best = c < best ? c : best;
+            }
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const uint32_t o = __shfl_xor(best, d, 64);
+            best = o < best ? o : best;
+        }
+        if (lane == 0 && best < ans[j]) ans[j] = best;
+        __syncthreads();
+    }
+}
+
+// LDS bytes of one k_local_search block for a given tau, and the set's hbits.
+static int32_t local_hbits(int32_t tau)
+{
+    int32_t b = 6;
+    while ((int64_t)(1 << b) * 2 < 3 * ((int64_t)tau + 64)) b++;
+    return b;
+}
+
+static size_t local_lds_bytes(int32_t tau, int32_t hbits)
+{
+    return (size_t)(1 << hbits) * 8 + 3 * 64 * 4 + (size_t)tau * 2 * 4 + (size_t)tau * 2 * 2;
+}
+
 }  // namespace cbfs
 
 using namespace cbfs;
@@ -114,4 +317,22 @@ extern "C" cbfs_status cbfs_query_batch(const cbfs_labels *L, int64_t q, const i
     hipError_t e = hipGetLastError();
     prof_end(tok);
     return e == hipSuccess ? CBFS_OK : hip_fail("query", e);
+}
+
+extern "C" cbfs_status cbfs_query_local(const cbfs_csr *g, int64_t q, const int32_t *s, const int32_t *t,
+                                        int32_t tau, uint32_t *ans, void *stream)
+{
+    if (!g || !g->row_ptr || !g->col || g->n < 1 || g->m < 0 || q < 0 || tau < 1 || tau > CBFS_LOCAL_TAU_MAX ||
+        (q > 0 && (!s || !t || !ans)))
+        return fail(CBFS_E_ARG, "cbfs_query_local: bad argument");
+    if (q == 0) return CBFS_OK;
+    const int32_t hbits = local_hbits(tau);
+    const size_t lds = local_lds_bytes(tau, hbits);
+    const int64_t blocks = q < (1 << 20) ? q : (1 << 20);
+    void *tok;
+    prof_begin(CBFS_KERNEL_LOCAL, (hipStream_t)stream, &tok);
+    k_local_search<<<(unsigned)blocks, 64, lds, (hipStream_t)stream>>>(g->row_ptr, g->col, q, s, t, tau, hbits, ans);
+    hipError_t e = hipGetLastError();
+    prof_end(tok);
+    return e == hipSuccess ? CBFS_OK : hip_fail("query_local", e);
 }

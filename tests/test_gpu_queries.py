@@ -109,3 +109,97 @@ def test_min_relative_on_landmark_clusters_of_each_diameter(dd):
         assert np.array_equal(st.cpu().numpy(), ost)
         assert np.array_equal(dist.cpu().numpy().view(np.uint32), od)
         assert np.array_equal(masks.cpu().numpy().view(np.uint64), om)
+
+
+def _local_graphs():
+    """(name, row_ptr, col): R-MAT with hubs (rows longer than a wave), a
+    sparse G(n, p) with isolated vertices and small components, a long path
+    (deep searches), and an R-MAT whose rows are stored in shuffled order."""
+    out = []
+    n, s, d = synth.rmat_edges(13, 16, seed=5)
+    rp, col, _ = oracle.clean_csr(n, s, d)
+    out.append(("rmat13", rp, col))
+    n, s, d = synth.random_graph(3000, 0.0006, 6)
+    rp, col, _ = oracle.clean_csr(n, s, d, flags=7)
+    out.append(("gnp_sparse", rp, col))
+    n = 5000
+    e = np.array([(i, i + 1) for i in range(n - 1)], np.int64)
+    rp, col, _ = oracle.clean_csr(n, e[:, 0], e[:, 1], flags=7)
+    out.append(("path", rp, col))
+    n, s, d = synth.rmat_edges(12, 8, seed=7)
+    rp, col, _ = oracle.clean_csr(n, s, d)
+    col = col.copy()
+    rng = np.random.default_rng(7)
+    for v in range(rp.size - 1):
+        rng.shuffle(col[rp[v]:rp[v + 1]])
+    out.append(("rmat12_shuffled_rows", rp, col))
+    return out
+
+
+@pytest.mark.parametrize("tau", [1, 2, 63, 64, 65, 200, 512, 2048])
+def test_local_search_matches_oracle(tau):
+    """Bidirectional local search (Appendix B) bit-exact against the oracle:
+    the local answer alone (ans pre-filled with none), on every graph."""
+    torch = _torch()
+    import paper_2410_17226_amd as P
+    for name, rp, col in _local_graphs():
+        nv = rp.size - 1
+        qs, qt = synth.query_pairs(nv, 1500, tau)
+        qs[:20] = qt[:20]                                   # s == t
+        deg = np.diff(rp)
+        hubs = np.argsort(-deg, kind="stable")[:20].astype(np.int32)
+        qs[20:40] = hubs                                    # hub endpoints
+        if (deg == 0).any():
+            qt[40:50] = np.nonzero(deg == 0)[0][:1]          # an isolated endpoint
+        print(f"[local] tau={tau} graph={name} n={nv} m={col.size} q={qs.size}", flush=True)
+        rp_d, col_d = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+        got = P.query_local(rp_d, col_d, torch.from_numpy(qs).cuda(), torch.from_numpy(qt).cuda(), tau)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy().view(np.uint32)
+        want = oracle.local_search(rp, col, qs, qt, tau)
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, (f"{name} tau={tau}: {bad.size} answers differ, e.g. pair {bad[0]} "
+                               f"({qs[bad[0]]}, {qt[bad[0]]}): {got[bad[0]]} vs {want[bad[0]]}")
+
+
+def test_local_search_combined_with_landmarks():
+    """ans = min(landmark answer, local answer): cbfs_query_batch, then
+    cbfs_query_local on the same output; never below the true distance."""
+    torch = _torch()
+    import paper_2410_17226_amd as P
+    n, s, d = synth.rmat_edges(12, 16, seed=9)
+    rp, col, _ = P.build_csr(n, s, d)
+    nv = rp.size - 1
+    cp, src = P.select_landmarks(rp, col, 16, 64, 2)
+    rp_d, col_d = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    dist, masks, st = P.run_batch(rp_d, col_d, cp, src, 1)
+    assert (st.cpu().numpy() == 0).all()
+    dvm, mvm = P.labels_pack(dist, masks, 1)
+    qs, qt = synth.query_pairs(nv, 4000, 9)
+    s_d, t_d = torch.from_numpy(qs).cuda(), torch.from_numpy(qt).cuda()
+    for tau in (64, 512):
+        ans = P.query_batch(dvm, mvm, 1, s_d, t_d)
+        landmark = ans.cpu().numpy().view(np.uint32).copy()
+        P.query_local(rp_d, col_d, s_d, t_d, tau, out=ans)
+        torch.cuda.synchronize()
+        got = ans.cpu().numpy().view(np.uint32)
+        local = oracle.local_search(rp, col, qs, qt, tau)
+        want = np.minimum(oracle.query_landmarks(rp, col, cp, src, qs, qt), local)
+        assert np.array_equal(landmark, oracle.query_landmarks(rp, col, cp, src, qs, qt))
+        assert np.array_equal(got, want)
+        true = oracle.pair_distances(rp, col, qs, qt)
+        ok = true != 0xFFFFFFFF
+        assert np.all(got[ok] >= true[ok])
+        assert np.sum(got != landmark) > 0  # the local search improved some answers
+
+
+def test_local_search_rejects_bad_tau():
+    torch = _torch()
+    import paper_2410_17226_amd as P
+    rp = torch.tensor([0, 1, 2], dtype=torch.int32, device="cuda")
+    col = torch.tensor([1, 0], dtype=torch.int32, device="cuda")
+    s = torch.zeros(4, dtype=torch.int32, device="cuda")
+    for tau in (0, P.LOCAL_TAU_MAX + 1):
+        with pytest.raises(P.CbfsError):
+            P.query_local(rp, col, s, s, tau)
+    assert P.query_local(rp, col, s[:0], s[:0], 8).numel() == 0
