@@ -422,7 +422,7 @@ cbfs_status cbfs_query_batch(const cbfs_labels *L, int64_t q, const int32_t *s, 
  * filled with CBFS_UNREACHED for the local answer alone.  g is the graph the
  * labels were built on (device CSR).  1 <= tau <= CBFS_LOCAL_TAU_MAX; the
  * search state lives in on-chip memory (8 bytes per set slot, the set holding
- * at least 1.5 (tau + 64) slots, plus 12 bytes per list entry: about 56 KiB
+ * at least 1.5 (tau + 64) slots, plus 12 bytes per list entry: about 50 KiB
  * per query at tau = 2048).  Vertex ids are not range-checked on the device.
  * Errors: CBFS_E_ARG (null pointers, sizes, tau out of range); CBFS_E_HIP.
  * ------------------------------------------------------------------------ */

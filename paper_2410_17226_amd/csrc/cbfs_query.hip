@@ -88,39 +88,42 @@ __global__ __launch_bounds__(256) void k_query(int64_t n, int32_t C, int32_t R, 
 //
 // One wave per query (a block of 64 threads), everything in LDS:
 //   keys[H], vals[H]  open-addressing set of the vertices one side has seen
-//                     (H a power of two >= 1.5 (tau + 64), so it never fills:
-//                     at most tau kept + 63 dropped keys per side);
+//                     (H >= 1.5 (tau + LS_STEP), so it never fills);
 //   ls/lsd[tau]       s side's discovery list and distances (kept for the
 //                     intersection), lt/ltd[tau] the t side's.
 // The search scans the arcs of up to 64 queued vertices as one concatenated
-// run, 64 consecutive arcs per step, one per lane, so a step's lanes hold arcs
-// in the order the sequential search would scan them.  A neighbour seen for
-// the first time in a step may occur on several lanes; the lowest lane (the
-// earliest arc) is its discoverer, found with an LDS atomic min on its slot,
-// and discoverers take list positions by ballot rank, which reproduces the
-// sequential discovery order.  Positions >= tau are dropped (the sequential
-// search stops there); their keys stay in the set marked dropped.
+// run, LS_STEP = 64 LS_ARCS consecutive arcs per step (arc 64 r + lane of the
+// step on lane `lane`, r < LS_ARCS), numbered in the order the sequential
+// search would scan them.  A neighbour seen for
+// the first time in a step may occur on several arcs; the earliest arc is its
+// discoverer, found with an LDS atomic min of the arc numbers on its slot, and
+// discoverers take list positions by ballot rank in arc order, which
+// reproduces the sequential discovery order.  Positions >= tau are dropped
+// (the sequential search stops there); their keys stay in the set marked
+// dropped, so the set holds at most tau + LS_STEP - 1 keys.
 //
-// vals states: PENDING (inserted in this step, owner not decided), a lane
-// index < 64 (owner being decided), KEPT | dist, DROPPED.
+// vals states: PENDING (inserted in this step, owner not decided), an arc
+// number < LS_STEP (owner being decided), KEPT | dist, DROPPED.
 constexpr uint32_t LS_PENDING = 0xFFFFFFFFu;
 constexpr uint32_t LS_DROPPED = 0xFFFFFFFEu;
 constexpr uint32_t LS_KEPT = 0x80000000u;
 constexpr int32_t LS_EMPTY = -1;
+constexpr int LS_ARCS = 1;                 // arcs per lane per step (4 measured no faster)
+constexpr int32_t LS_STEP = 64 * LS_ARCS;  // arcs per step
 
-__device__ __forceinline__ uint32_t ls_hash(int32_t v, int32_t hbits)
+// Multiplicative hash scaled to [0, H) (H need not be a power of two).
+__device__ __forceinline__ uint32_t ls_hash(int32_t v, uint32_t H)
 {
-    return ((uint32_t)v * 2654435761u) >> (32 - hbits);
+    return (uint32_t)(((uint64_t)((uint32_t)v * 2654435761u) * H) >> 32);
 }
 
 __device__ __forceinline__ bool ls_kept(uint32_t val) { return (val >> 30) == 2u; }
 
 // Slot of v, inserting v if absent (lanes racing for one empty slot: the CAS
 // lets one key in, the others probe on unless they carry the same key).
-__device__ __forceinline__ uint32_t ls_insert(int32_t *keys, int32_t hbits, int32_t v)
+__device__ __forceinline__ uint32_t ls_insert(int32_t *keys, uint32_t H, int32_t v)
 {
-    const uint32_t mask = (1u << hbits) - 1u;
-    uint32_t slot = ls_hash(v, hbits);
+    uint32_t slot = ls_hash(v, H);
     while (true) {
         const int32_t k = keys[slot];
         if (k == v) return slot;
@@ -128,37 +131,35 @@ __device__ __forceinline__ uint32_t ls_insert(int32_t *keys, int32_t hbits, int3
             const int32_t old = atomicCAS(&keys[slot], LS_EMPTY, v);
             if (old == LS_EMPTY || old == v) return slot;
         }
-        slot = (slot + 1) & mask;
+        slot = slot + 1 == H ? 0u : slot + 1;
     }
 }
 
-__device__ __forceinline__ uint32_t ls_find(const int32_t *keys, const uint32_t *vals, int32_t hbits, int32_t v)
+__device__ __forceinline__ uint32_t ls_find(const int32_t *keys, const uint32_t *vals, uint32_t H, int32_t v)
 {
-    const uint32_t mask = (1u << hbits) - 1u;
-    uint32_t slot = ls_hash(v, hbits);
+    uint32_t slot = ls_hash(v, H);
     while (true) {
         const int32_t k = keys[slot];
         if (k == v) return vals[slot];
         if (k == LS_EMPTY) return LS_DROPPED;
-        slot = (slot + 1) & mask;
+        slot = slot + 1 == H ? 0u : slot + 1;
     }
 }
 
 // tau-bounded FIFO BFS from root; leaves its set in keys/vals and its
 // discovery list in list/listd; returns the list length.  Wave-uniform.
 __device__ int32_t ls_search(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, int32_t root,
-                             int32_t tau, int32_t hbits, int32_t *keys, uint32_t *vals, int32_t *list,
+                             int32_t tau, uint32_t H, int32_t *keys, uint32_t *vals, int32_t *list,
                              uint16_t *listd, int32_t *pre_excl, int32_t *pre_base, int32_t *pre_dist)
 {
     const int lane = threadIdx.x;
-    const int32_t H = 1 << hbits;
-    for (int32_t i = lane; i < H; i += 64) {
+    for (uint32_t i = lane; i < H; i += 64) {
         keys[i] = LS_EMPTY;
         vals[i] = LS_PENDING;
     }
     __syncthreads();
     if (lane == 0) {
-        const uint32_t slot = ls_insert(keys, hbits, root);
+        const uint32_t slot = ls_insert(keys, H, root);
         vals[slot] = LS_KEPT;
         list[0] = root;
         listd[0] = 0;
@@ -186,41 +187,59 @@ __device__ int32_t ls_search(const int32_t *__restrict__ row_ptr, const int32_t 
         pre_base[lane] = base;
         pre_dist[lane] = pd + 1;
         __syncthreads();
-        for (int32_t a0 = 0; a0 < total && cnt < tau; a0 += 64) {
-            const int32_t g = a0 + lane;
-            bool fresh = false;
-            uint32_t slot = 0;
-            int32_t v = 0, dv = 0;
-            if (g < total) {
-                int32_t lo = 0, hi = gn - 1;  // the last queued vertex whose arcs start at or before g
-                while (lo < hi) {
-                    const int32_t mid = (lo + hi + 1) >> 1;
-                    if (pre_excl[mid] <= g) lo = mid;
-                    else hi = mid - 1;
-                }
-                v = col[pre_base[lo] + (g - pre_excl[lo])];
-                dv = pre_dist[lo];
-                slot = ls_insert(keys, hbits, v);
-            }
-            __syncthreads();
-            if (g < total) fresh = vals[slot] == LS_PENDING;
-            __syncthreads();
-            if (fresh) atomicMin(&vals[slot], (uint32_t)lane);
-            __syncthreads();
-            const bool first = fresh && vals[slot] == (uint32_t)lane;
-            const uint64_t won = __ballot(first);
-            __syncthreads();
-            if (first) {
-                const int32_t pos = cnt + (int32_t)__popcll(won & ((1ull << lane) - 1ull));
-                if (pos < tau) {
-                    list[pos] = v;
-                    listd[pos] = (uint16_t)dv;
-                    vals[slot] = LS_KEPT | (uint32_t)dv;
-                } else {
-                    vals[slot] = LS_DROPPED;
+        for (int32_t a0 = 0; a0 < total && cnt < tau; a0 += LS_STEP) {
+            int32_t v[LS_ARCS], dv[LS_ARCS];
+            uint32_t slot[LS_ARCS];
+            bool fresh[LS_ARCS];
+            int32_t lo = 0;
+#pragma unroll
+            for (int r = 0; r < LS_ARCS; r++) {  // owners, then the column reads, all in flight together
+                const int32_t g = a0 + 64 * r + lane;
+                v[r] = -1;
+                dv[r] = 0;
+                if (g < total) {
+                    int32_t hi = gn - 1;  // the last queued vertex whose arcs start at or before g
+                    while (lo < hi) {
+                        const int32_t mid = (lo + hi + 1) >> 1;
+                        if (pre_excl[mid] <= g) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    v[r] = col[pre_base[lo] + (g - pre_excl[lo])];
+                    dv[r] = pre_dist[lo];
                 }
             }
-            cnt += (int32_t)__popcll(won);
+#pragma unroll
+            for (int r = 0; r < LS_ARCS; r++) slot[r] = v[r] >= 0 ? ls_insert(keys, H, v[r]) : 0u;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < LS_ARCS; r++) fresh[r] = v[r] >= 0 && vals[slot[r]] == LS_PENDING;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < LS_ARCS; r++)
+                if (fresh[r]) atomicMin(&vals[slot[r]], (uint32_t)(64 * r + lane));
+            __syncthreads();
+            uint64_t won[LS_ARCS];
+#pragma unroll
+            for (int r = 0; r < LS_ARCS; r++) {
+                fresh[r] = fresh[r] && vals[slot[r]] == (uint32_t)(64 * r + lane);  // the earliest arc
+                won[r] = __ballot(fresh[r]);
+            }
+            __syncthreads();
+            const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+            for (int r = 0; r < LS_ARCS; r++) {
+                if (fresh[r]) {
+                    const int32_t pos = cnt + (int32_t)__popcll(won[r] & below);
+                    if (pos < tau) {
+                        list[pos] = v[r];
+                        listd[pos] = (uint16_t)dv[r];
+                        vals[slot[r]] = LS_KEPT | (uint32_t)dv[r];
+                    } else {
+                        vals[slot[r]] = LS_DROPPED;
+                    }
+                }
+                cnt += (int32_t)__popcll(won[r]);
+            }
             cnt = cnt < tau ? cnt : tau;
             __syncthreads();
         }
@@ -232,10 +251,9 @@ __device__ int32_t ls_search(const int32_t *__restrict__ row_ptr, const int32_t 
 __global__ __launch_bounds__(64) void k_local_search(const int32_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col, int64_t q,
                                                      const int32_t *qs, const int32_t *qt, int32_t tau,
-                                                     int32_t hbits, uint32_t *ans)
+                                                     uint32_t H, uint32_t *ans)
 {
     extern __shared__ int32_t lds[];
-    const int32_t H = 1 << hbits;
     int32_t *keys = lds;
     uint32_t *vals = (uint32_t *)(keys + H);
     int32_t *pre_excl = (int32_t *)(vals + H);
@@ -247,12 +265,12 @@ __global__ __launch_bounds__(64) void k_local_search(const int32_t *__restrict__
     uint16_t *ltd = lsd + tau;
     const int lane = threadIdx.x;
     for (int64_t j = blockIdx.x; j < q; j += gridDim.x) {
-        const int32_t cs = ls_search(row_ptr, col, qs[j], tau, hbits, keys, vals, ls, lsd, pre_excl, pre_base,
+        const int32_t cs = ls_search(row_ptr, col, qs[j], tau, H, keys, vals, ls, lsd, pre_excl, pre_base,
                                      pre_dist);
-        ls_search(row_ptr, col, qt[j], tau, hbits, keys, vals, lt, ltd, pre_excl, pre_base, pre_dist);
+        ls_search(row_ptr, col, qt[j], tau, H, keys, vals, lt, ltd, pre_excl, pre_base, pre_dist);
         uint32_t best = CBFS_UNREACHED;
         for (int32_t k = lane; k < cs; k += 64) {
-            const uint32_t val = ls_find(keys, vals, hbits, ls[k]);
+            const uint32_t val = ls_find(keys, vals, H, ls[k]);
             if (ls_kept(val)) {
                 const uint32_t c = (uint32_t)lsd[k] + (val & ~LS_KEPT);
                 best = c < best ? c : best;
@@ -268,17 +286,18 @@ __global__ __launch_bounds__(64) void k_local_search(const int32_t *__restrict__
     }
 }
 
-// LDS bytes of one k_local_search block for a given tau, and the set's hbits.
-static int32_t local_hbits(int32_t tau)
+// Set slots for a given tau: 1.5 times the most keys one side inserts (tau
+// kept + LS_STEP - 1 dropped), rounded up to a multiple of 64; and the LDS
+// bytes of one k_local_search block.
+static uint32_t local_set_slots(int32_t tau)
 {
-    int32_t b = 6;
-    while ((int64_t)(1 << b) * 2 < 3 * ((int64_t)tau + 64)) b++;
-    return b;
+    const int64_t need = (3 * ((int64_t)tau + LS_STEP) + 1) / 2;
+    return (uint32_t)((need + 63) / 64 * 64);
 }
 
-static size_t local_lds_bytes(int32_t tau, int32_t hbits)
+static size_t local_lds_bytes(int32_t tau, uint32_t H)
 {
-    return (size_t)(1 << hbits) * 8 + 3 * 64 * 4 + (size_t)tau * 2 * 4 + (size_t)tau * 2 * 2;
+    return (size_t)H * 8 + 3 * 64 * 4 + (size_t)tau * 2 * 4 + (size_t)tau * 2 * 2;
 }
 
 }  // namespace cbfs
@@ -326,12 +345,12 @@ extern "C" cbfs_status cbfs_query_local(const cbfs_csr *g, int64_t q, const int3
         (q > 0 && (!s || !t || !ans)))
         return fail(CBFS_E_ARG, "cbfs_query_local: bad argument");
     if (q == 0) return CBFS_OK;
-    const int32_t hbits = local_hbits(tau);
-    const size_t lds = local_lds_bytes(tau, hbits);
+    const uint32_t H = local_set_slots(tau);
+    const size_t lds = local_lds_bytes(tau, H);
     const int64_t blocks = q < (1 << 20) ? q : (1 << 20);
     void *tok;
     prof_begin(CBFS_KERNEL_LOCAL, (hipStream_t)stream, &tok);
-    k_local_search<<<(unsigned)blocks, 64, lds, (hipStream_t)stream>>>(g->row_ptr, g->col, q, s, t, tau, hbits, ans);
+    k_local_search<<<(unsigned)blocks, 64, lds, (hipStream_t)stream>>>(g->row_ptr, g->col, q, s, t, tau, H, ans);
     hipError_t e = hipGetLastError();
     prof_end(tok);
     return e == hipSuccess ? CBFS_OK : hip_fail("query_local", e);
