@@ -202,8 +202,8 @@ enum {
 /* Tuning knobs (nullable: all defaults).  No knob changes any output bit. */
 typedef struct {
     int32_t mode;              /* CBFS_MODE_*                                          */
-    int32_t group_words;       /* words per vertex of a cluster group: 0 = auto (8 for
-                                  clusters of <= 64 sources, 16 for larger ones, the
+    int32_t group_words;       /* words per vertex of a cluster group: 0 = auto (16,
+                                  fewer when the batch has fewer clusters; the
                                   cluster's words on sparse graphs), else a multiple
                                   of W in {1,2,4,8,16}                                 */
     int32_t concurrent_groups; /* group slots searched side by side: 0 = auto          */

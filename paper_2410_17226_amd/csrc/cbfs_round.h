@@ -17,6 +17,15 @@ struct PushSmem {
     Stager<STAGE_CAP> st;
 };
 
+// Lanes per vertex in the pull: a state of W >= 16 words is split over
+// H = W / 8 lanes of 8 words each (register pressure), the lanes of a vertex
+// lying 64 / H apart in the wave (one half-wave per half for H = 2).
+template <int W>
+constexpr int pull_split()
+{
+    return W >= 16 ? W / 8 : 1;
+}
+
 template <int W>
 struct PullSmem {
     uint16_t rend[TILE_ITEMS + 2];           // row_end of the tile's rows minus tile_edge (clamped)
@@ -28,11 +37,12 @@ struct PullSmem {
     unsigned long long degsum;
     long long base;
     union {
-        uint64_t part[BLOCK][W];             // walk: partial sets of rows shared by threads, by first thread
+        uint64_t part[BLOCK / pull_split<W>()][W];  // walk: partial sets of rows shared by walkers, by first walker
         struct {
             uint16_t arow[TILE_ITEMS];       // row of each of the tile's arcs, minus tile_row
             uint64_t out_acc[WAVES][W];      // a wave's share of the row still open at its range end
             uint64_t pend_acc[WAVES][W];     // a wave's share of a row it closes that began earlier
+            uint64_t cacc[WAVES][W];         // the OR so far of the row a wave carries between steps
             int32_t out_row[WAVES], pend_row[WAVES];
         } wv;                                // wave form
     };
@@ -245,6 +255,7 @@ __device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &
 // phase of the frontier vertices in the range runs here as well.
 // hubs[0 .. hubs[HUB_MAX]) lists the frontier's vertices.
 // ---------------------------------------------------------------------------
+static_assert(WAVES * 4 + 4 <= 64, "the merges after a wave-form pass run in wave 0");
 static_assert(HUB_RANGE == BLOCK && HUB_MAX <= BLOCK, "one owned target and one frontier vertex per thread");
 static_assert(HUB_RANGE % 64 == 0, "a block owns whole frontier-bitmap words");
 
@@ -500,14 +511,16 @@ __device__ __forceinline__ PullTile pull_coords(const GraphArgs &gr, int32_t t)
     return T;
 }
 
-// OR x (non-empty, bits v lacked in round i) into nxt(v) for a row whose arcs
-// span several tiles; true if this call won v's claim in the frontier bitmap.
-template <int W>
-__device__ __forceinline__ bool merge_global(uint64_t *nxt, uint64_t *bits_next, int32_t v, const uint64_t (&x)[W])
+// OR x (non-empty, bits v lacked in round i) into words [hw, hw + WL) of
+// nxt(v) (W words per vertex) for a row whose arcs span several tiles; true
+// if this call won v's claim in the frontier bitmap.
+template <int WL, int W>
+__device__ __forceinline__ bool merge_global(uint64_t *nxt, uint64_t *bits_next, int32_t v, int hw,
+                                             const uint64_t (&x)[WL])
 {
-    uint64_t *p = nxt + (size_t)v * W;
+    uint64_t *p = nxt + (size_t)v * W + hw;
 #pragma unroll
-    for (int w = 0; w < W; w++)
+    for (int w = 0; w < WL; w++)
         if (x[w]) or64(p + w, x[w]);
     const unsigned long long bit = 1ull << (v & 63);
     const unsigned long long old = atomicOr(reinterpret_cast<unsigned long long *>(bits_next + (v >> 6)), bit);
@@ -536,9 +549,10 @@ __device__ __forceinline__ uint64_t dpp64(uint64_t x)
 // row of 16 lanes (DPP row_shr), then the ends of rows 0 and 2 into rows 1 and
 // 3 (row_bcast:15), then the end of row 1 into rows 2 and 3 (row_bcast:31):
 // all in VALU, no LDS permutes.
-template <int W>
+template <int W, int AL = 64>
 __device__ __forceinline__ void seg_or_scan(uint64_t (&x)[W], int lane, int first)
 {
+    static_assert(AL == 64 || AL == 32 || AL == 16, "segments of 16, 32 or 64 lanes");
     // one AND-OR per dword: the lane's mask (all ones when the shifted lane
     // lies in its segment) is formed once per level
     auto level = [&](auto ctrl, auto rmask, bool take) {
@@ -566,8 +580,65 @@ __device__ __forceinline__ void seg_or_scan(uint64_t (&x)[W], int lane, int firs
     level(c2{}, all{}, lane - 2 >= first);
     level(c4{}, all{}, lane - 4 >= first);
     level(c8{}, all{}, lane - 8 >= first);
-    level(b15{}, std::integral_constant<int, 0xA>{}, (lane & 16) != 0 && (lane & ~15) - 1 >= first);
-    level(b31{}, std::integral_constant<int, 0xC>{}, lane >= 32 && 31 >= first);
+    // with AL < 64 the wave holds 64 / AL independent scans of AL lanes each
+    // (lane is the index inside its scan): the cross-row levels stop there
+    if constexpr (AL >= 32)
+        level(b15{}, std::integral_constant<int, 0xA>{}, (lane & 16) != 0 && (lane & ~15) - 1 >= first);
+    if constexpr (AL == 64) level(b31{}, std::integral_constant<int, 0xC>{}, lane >= 32 && 31 >= first);
+}
+
+// Decisions shared by the H lanes of one vertex (the lanes in grp, all
+// active): any / all of their predicates.
+template <int H>
+__device__ __forceinline__ bool group_any(bool p, uint64_t grp)
+{
+    if constexpr (H == 1) return p;
+    else return (__ballot(p) & grp) != 0;
+}
+template <int H>
+__device__ __forceinline__ bool group_all(bool p, uint64_t grp)
+{
+    if constexpr (H == 1) return p;
+    else return (__ballot(p) & grp) == grp;
+}
+
+// True when a | b (this lane's share of a set: words [hw, hw + WL) for the
+// lane's share index hw / WL) equals the complete set on every lane of the
+// lane's group grp (all of them active).  For H > 1 each share's words are
+// compared as scalars, one ballot per word, so no vector register holds a
+// per-lane copy of the complete set.
+template <int H, int WL>
+__device__ __forceinline__ bool share_complete(const uint64_t (&a)[WL], const uint64_t (&b)[WL],
+                                               const uint64_t *gfull, uint64_t grp)
+{
+    if constexpr (H == 1) {
+        bool f = true;
+#pragma unroll
+        for (int w = 0; w < WL; w++) f &= (a[w] | b[w]) == gfull[w];
+        return f;
+    } else {
+        constexpr int AL = 64 / H;
+        uint64_t all = 0;  // lanes whose share equals the complete set's
+#pragma unroll
+        for (int j = 0; j < H; j++) {
+            uint64_t m = ((AL == 64 ? 0ull : (1ull << AL)) - 1ull) << (j * AL);
+#pragma unroll
+            for (int w = 0; w < WL; w++) m &= __ballot((a[w] | b[w]) == gfull[j * WL + w]);
+            all |= m;
+        }
+        return (all & grp) == grp;
+    }
+}
+
+// Lanes al, al + AL, al + 2 AL, ... of a wave (the H lanes of one vertex).
+template <int H>
+__device__ __forceinline__ uint64_t lane_group(int al)
+{
+    constexpr int AL = 64 / H;
+    uint64_t m = 0;
+#pragma unroll
+    for (int j = 0; j < H; j++) m |= 1ull << (al + AL * j);
+    return m;
 }
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t x, int src)
@@ -583,28 +654,40 @@ constexpr int pull_batch()
     return W <= 2 ? 8 : (W <= 4 ? 4 : 1);
 }
 
-// PULL_WALK arc phase and vertex phase (see above).
+// PULL_WALK arc phase and vertex phase (see above).  With H = pull_split<W>()
+// lanes per vertex, lanes al, al + AL, ... (AL = 64 / H) of a wave form one
+// walker: they walk the same items with the same control flow, each with its
+// WL = W / H words of every set, and take shared decisions (set complete,
+// anything new) together.
 template <int W, int WC>
 __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                           const OutArgs &o, int32_t round, const PullTile &T)
 {
-    constexpr int NB = pull_batch<W>();
+    constexpr int H = pull_split<W>();
+    constexpr int WL = W / H;
+    constexpr int AL = 64 / H;
+    constexpr int WALKERS = BLOCK / H;
+    constexpr int IPW = IPT * H;  // items per walker
+    constexpr int NB = pull_batch<WL>();
     const uint64_t *cur = cur_buf(s, round);
     uint64_t *nxt = nxt_buf(s, round);
     const uint64_t *bits_cur = bits_buf(s, round % 3);
     uint64_t *bits_next = bits_buf(s, (round + 1) % 3);
     const int32_t r0 = T.r0, e0 = T.e0, r1 = T.r1;
-#pragma unroll
-    for (int w = 0; w < W; w++) sm.part[threadIdx.x][w] = 0;
+    const int lane = threadIdx.x & 63, al = lane % AL;
+    const int hw = (lane / AL) * WL;  // this lane's first word of a set
+    const int walker = (int)(threadIdx.x >> 6) * AL + al;
+    const uint64_t grp = lane_group<H>(al);
+    for (int i = threadIdx.x; i < WALKERS * W; i += BLOCK) (&sm.part[0][0])[i] = 0;
     __syncthreads();
     // row_end[r] for a row of the tile (exact for r < r1; past e1 for r1)
     auto rend_of = [&](int32_t r) { return e0 + (int32_t)sm.rend[r - r0]; };
     auto rstart_of = [&](int32_t r) { return r == r0 ? T.start_r0 : e0 + (int32_t)sm.rend[r - 1 - r0]; };
 
-    // this thread's merge-path start inside the tile
-    int32_t rel = (int32_t)threadIdx.x * IPT;
+    // this walker's merge-path start inside the tile
+    int32_t rel = walker * IPW;
     if (rel > T.tile_items) rel = T.tile_items;
-    int32_t my_end = ((int32_t)threadIdx.x + 1) * IPT;
+    int32_t my_end = (walker + 1) * IPW;
     if (my_end > T.tile_items) my_end = T.tile_items;
     const int32_t my_start = rel;
     int32_t row, edge;
@@ -620,27 +703,26 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         edge = e0 + (rel - lo);
     }
 
-    uint64_t full[W];
-#pragma unroll
-    for (int w = 0; w < W; w++) full[w] = g.full[w];
 
     // a local row with new bits stores nxt(v) here; a row of F_i without any
     // gets nxt(v) = Seen_i(v) in the vertex pass
-    auto finish_local = [&](int32_t v, const uint64_t (&cv)[W], const uint64_t (&acc)[W]) {
+    auto finish_local = [&](int32_t v, const uint64_t (&cv)[WL], const uint64_t (&acc)[WL]) {
         bool any = false;
 #pragma unroll
-        for (int w = 0; w < W; w++) any |= acc[w] != 0;
-        if (!any) return;
-        uint64_t nv[W];
+        for (int w = 0; w < WL; w++) any |= acc[w] != 0;
+        if (!group_any<H>(any, grp)) return;
+        uint64_t nv[WL];
 #pragma unroll
-        for (int w = 0; w < W; w++) nv[w] = cv[w] | acc[w];
-        store_words<W>(nxt + (size_t)v * W, nv);
-        const int32_t k = v - r0;
-        atomicOr(reinterpret_cast<unsigned long long *>(&sm.stored[k >> 6]), 1ull << (k & 63));
-        pull_claim(sm, T, v);
+        for (int w = 0; w < WL; w++) nv[w] = cv[w] | acc[w];
+        store_words<WL>(nxt + (size_t)v * W + hw, nv);
+        if (hw == 0) {
+            const int32_t k = v - r0;
+            atomicOr(reinterpret_cast<unsigned long long *>(&sm.stored[k >> 6]), 1ull << (k & 63));
+            pull_claim(sm, T, v);
+        }
     };
 
-    // a local row owned here whose first arcs other threads scanned: its own
+    // a local row owned here whose first arcs other walkers scanned: its own
     // partial set joins theirs in LDS and the row is finished after the barrier
     int32_t pend = -1;
     int32_t rstart = rel < my_end ? rstart_of(row) : 0;
@@ -658,13 +740,13 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
             rstart = rend;
             continue;
         }
-        uint64_t cv[W], acc[W];
+        uint64_t cv[WL], acc[WL];
         // software pipeline: the row's own set, the first two batches'
         // neighbour ids and the first batch's frontier words are requested
         // together; in the loop, batch k's Seen_i(u) gathers go out with
         // batch k+1's frontier words and batch k+2's ids, so each batch waits
         // for its own gathers only
-        load_words<W>(cur + (size_t)row * W, cv);
+        load_words<WL>(cur + (size_t)row * W + hw, cv);
         int32_t u0[NB], u1[NB];
         uint64_t b0[NB];
 #pragma unroll
@@ -674,12 +756,9 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         }
 #pragma unroll
         for (int j = 0; j < NB; j++) b0[j] = bits_cur[u0[j] >> 6];
-        bool fin = true;
 #pragma unroll
-        for (int w = 0; w < W; w++) {
-            acc[w] = 0;
-            fin &= cv[w] == full[w];
-        }
+        for (int w = 0; w < WL; w++) acc[w] = 0;
+        bool fin = share_complete<H, WL>(cv, acc, g.full, grp);
         for (int32_t e = edge; e < seg_end && !fin; e += NB) {
             int32_t u[NB];
             uint64_t hm[NB];  // all ones for a neighbour whose set counts
@@ -689,9 +768,9 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
                 hm[j] = hit ? ~0ull : 0ull;
                 u[j] = hit ? u0[j] : row;  // keep the load in place, its value is masked off
             }
-            uint64_t cu[NB][W];
+            uint64_t cu[NB][WL];
 #pragma unroll
-            for (int j = 0; j < NB; j++) load_words<W>(cur + (size_t)u[j] * W, cu[j]);
+            for (int j = 0; j < NB; j++) load_words<WL>(cur + (size_t)u[j] * W + hw, cu[j]);
 #pragma unroll
             for (int j = 0; j < NB; j++) b0[j] = bits_cur[u1[j] >> 6];
 #pragma unroll
@@ -699,15 +778,13 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
                 u0[j] = u1[j];
                 u1[j] = (e + 2 * NB + j < seg_end) ? gr.col[e + 2 * NB + j] : row;
             }
-            bool f = true;
 #pragma unroll
-            for (int w = 0; w < W; w++) {
+            for (int w = 0; w < WL; w++) {
 #pragma unroll
                 for (int j = 0; j < NB; j++) acc[w] |= cu[j][w] & hm[j];
                 acc[w] &= ~cv[w];
-                f &= (acc[w] | cv[w]) == full[w];
             }
-            fin = f;
+            fin = share_complete<H, WL>(acc, cv, g.full, grp);
         }
         rel += seg_end - edge;
         edge = seg_end;
@@ -715,16 +792,16 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         const int32_t first_item = (row - r0) + (rstart - e0);
         const bool local = first_item >= 0 && row < r1;
         if (!local) {
-            // crosses a tile edge: merge by global atomics
+            // crosses a tile edge: merge by global atomics (each lane its words)
             bool any = false;
 #pragma unroll
-            for (int w = 0; w < W; w++) any |= acc[w] != 0;
-            if (any && merge_global<W>(nxt, bits_next, row, acc)) pull_claim(sm, T, row);
+            for (int w = 0; w < WL; w++) any |= acc[w] != 0;
+            if (any && merge_global<WL, W>(nxt, bits_next, row, hw, acc)) pull_claim(sm, T, row);
         } else if (!owns_end || first_item < my_start) {
-            // a local row other threads share: into the slot of its first thread
-            uint64_t *slot = sm.part[first_item / IPT];
+            // a local row other walkers share: into the slot of its first walker
+            uint64_t *slot = sm.part[first_item / IPW] + hw;
 #pragma unroll
-            for (int w = 0; w < W; w++)
+            for (int w = 0; w < WL; w++)
                 if (acc[w]) atomicOr(reinterpret_cast<unsigned long long *>(slot + w), acc[w]);
             if (owns_end) pend = row;
         } else {
@@ -738,11 +815,11 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     __syncthreads();
     if (pend >= 0) {
         const int32_t first_item = (pend - r0) + (rstart_of(pend) - e0);
-        const uint64_t *slot = sm.part[first_item / IPT];
-        uint64_t cv[W], acc[W];
-        load_words<W>(cur + (size_t)pend * W, cv);
+        const uint64_t *slot = sm.part[first_item / IPW] + hw;
+        uint64_t cv[WL], acc[WL];
+        load_words<WL>(cur + (size_t)pend * W + hw, cv);
 #pragma unroll
-        for (int w = 0; w < W; w++) acc[w] = slot[w];
+        for (int w = 0; w < WL; w++) acc[w] = slot[w];
         finish_local(pend, cv, acc);
     }
     __syncthreads();
@@ -766,20 +843,26 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     __syncthreads();
 }
 
-// PULL_WAVE arc phase and vertex phase (see above).
+// PULL_WAVE arc phase and vertex phase (see above).  With H = pull_split<W>()
+// lanes per vertex a step covers AL = 64 / H arcs: arc k of the step on lanes
+// k, k + AL, ..., each lane with its WL = W / H words of every set; the
+// segmented scan runs within each group of AL lanes, and the lanes of one arc
+// take shared decisions (anything new, set complete) together.
 template <int W, int WC>
 __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                           const OutArgs &o, int32_t round, const PullTile &T)
 {
+    constexpr int H = pull_split<W>();
+    constexpr int WL = W / H;
+    constexpr int AL = 64 / H;
     const uint64_t *cur = cur_buf(s, round);
     uint64_t *nxt = nxt_buf(s, round);
     const uint64_t *bits_cur = bits_buf(s, round % 3);
     uint64_t *bits_next = bits_buf(s, (round + 1) % 3);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int al = lane % AL, h = lane / AL, hw = h * WL;
+    const uint64_t grp = lane_group<H>(al);
     const int32_t r0 = T.r0, e0 = T.e0, r1 = T.r1, tile_rows = T.tile_rows, tile_edges = T.tile_edges;
-    uint64_t full[W];
-#pragma unroll
-    for (int w = 0; w < W; w++) full[w] = g.full[w];
 
     for (int32_t k = threadIdx.x; k < tile_edges; k += BLOCK) sm.wv.arow[k] = 0;
     if (threadIdx.x < WAVES) {
@@ -819,127 +902,133 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
 
     const int32_t wa = (int32_t)(((int64_t)tile_edges * wv) / WAVES);
     const int32_t wb = (int32_t)(((int64_t)tile_edges * (wv + 1)) / WAVES);
-    // a row whose every contribution from this tile is in x; cv holds cur(v)
-    auto finish_row_cv = [&](int32_t k, const uint64_t (&x)[W], uint64_t (&cv)[W]) {
+    // a row whose every contribution from this tile is in x (words
+    // [hx, hx + WL) of each set; the lanes of gx hold the other words); cv
+    // holds those words of cur(v)
+    auto finish_row_cv = [&](int32_t k, const uint64_t (&x)[WL], uint64_t (&cv)[WL], int hx, uint64_t gx) {
         const int32_t v = r0 + k;
-        uint64_t acc[W];
+        uint64_t acc[WL];
         bool any = false;
 #pragma unroll
-        for (int w = 0; w < W; w++) {
+        for (int w = 0; w < WL; w++) {
             acc[w] = x[w] & ~cv[w];
             any |= acc[w] != 0;
         }
-        if (!any) return;
         if (v >= T.loc_lo && v < r1) {
+            if (!group_any<H>(any, gx)) return;
 #pragma unroll
-            for (int w = 0; w < W; w++) cv[w] |= acc[w];
-            store_words<W>(nxt + (size_t)v * W, cv);
-            atomicOr(reinterpret_cast<unsigned long long *>(&sm.stored[k >> 6]), 1ull << (k & 63));
-            pull_claim(sm, T, v);
-        } else if (merge_global<W>(nxt, bits_next, v, acc)) {
+            for (int w = 0; w < WL; w++) cv[w] |= acc[w];
+            store_words<WL>(nxt + (size_t)v * W + hx, cv);
+            if (hx == 0) {
+                atomicOr(reinterpret_cast<unsigned long long *>(&sm.stored[k >> 6]), 1ull << (k & 63));
+                pull_claim(sm, T, v);
+            }
+        } else if (any && merge_global<WL, W>(nxt, bits_next, v, hx, acc)) {
             pull_claim(sm, T, v);
         }
     };
-    auto finish_row = [&](int32_t k, const uint64_t (&x)[W]) {
+    auto finish_row = [&](int32_t k, const uint64_t (&x)[WL], int hx, uint64_t gx) {
         bool nz = false;
 #pragma unroll
-        for (int w = 0; w < W; w++) nz |= x[w] != 0;
-        if (!nz) return;
-        uint64_t cv[W];
-        load_words<W>(cur + (size_t)(r0 + k) * W, cv);
-        finish_row_cv(k, x, cv);
+        for (int w = 0; w < WL; w++) nz |= x[w] != 0;
+        if (!group_any<H>(nz, gx)) return;
+        uint64_t cv[WL];
+        load_words<WL>(cur + (size_t)(r0 + k) * W + hx, cv);
+        finish_row_cv(k, x, cv, hx, gx);
     };
     // a row's share of this wave's range ends with x: finished here, or left
     // for the merge below (begun in an earlier wave's range, or open past it)
-    auto close_row = [&](int32_t k, const uint64_t (&x)[W]) {
+    auto close_row = [&](int32_t k, const uint64_t (&x)[WL]) {
         if (rstart_off(k) >= wa) {
-            finish_row(k, x);
+            finish_row(k, x, hw, grp);
         } else {
             sm.wv.pend_row[wv] = k;
 #pragma unroll
-            for (int w = 0; w < W; w++) sm.wv.pend_acc[wv][w] = x[w];
+            for (int w = 0; w < WL; w++) sm.wv.pend_acc[wv][hw + w] = x[w];
         }
     };
-    auto leave_row = [&](int32_t k, const uint64_t (&x)[W]) {
+    auto leave_row = [&](int32_t k, const uint64_t (&x)[WL]) {
         sm.wv.out_row[wv] = k;
 #pragma unroll
-        for (int w = 0; w < W; w++) sm.wv.out_acc[wv][w] = x[w];
+        for (int w = 0; w < WL; w++) sm.wv.out_acc[wv][hw + w] = x[w];
     };
 
     int32_t crow = -1;  // row carried from the wave's previous step (wave-uniform)
-    uint64_t cacc[W], ccv[W];  // its OR so far, and its cur words
+    uint64_t ccv[WL];   // its cur words (this lane's share); its OR so far is in sm.wv.cacc[wv]
 #pragma unroll
-    for (int w = 0; w < W; w++) cacc[w] = ccv[w] = 0;
+    for (int w = 0; w < WL; w++) ccv[w] = 0;
     for (int32_t base = wa; base < wb;) {
-        int32_t next = base + 64;
-        const int32_t k = base + lane;
+        int32_t next = base + AL;
+        const int32_t k = base + al;
         const bool in = k < wb;
         const int32_t rk = in ? (int32_t)sm.wv.arow[k] : 0;  // a valid row index on every lane
         const bool active = in && !((sm.fin[rk >> 6] >> (rk & 63)) & 1ull);
         const int32_t re = in ? (int32_t)sm.rend[rk] : 0;
         // a row that will carry out of this step and was not carried into it:
         // its words go out with this step's gathers, so the completeness test
-        // at the step's end already covers its first 64 arcs
+        // at the step's end already covers its first AL arcs
         {
-            const int32_t r63 = __builtin_amdgcn_readlane(rk, 63);
-            const int32_t re63 = __builtin_amdgcn_readlane(re, 63);
-            if (base + 64 < wb && re63 != base + 64 && r63 != crow)
-                load_words<W>(cur + (size_t)(r0 + r63) * W, ccv);
+            const int32_t rl = __builtin_amdgcn_readlane(rk, AL - 1);
+            const int32_t rel = __builtin_amdgcn_readlane(re, AL - 1);
+            if (base + AL < wb && rel != base + AL && rl != crow)
+                load_words<WL>(cur + (size_t)(r0 + rl) * W + hw, ccv);
         }
-        uint64_t x[W];
+        uint64_t x[WL];
 #pragma unroll
-        for (int w = 0; w < W; w++) x[w] = 0;
+        for (int w = 0; w < WL; w++) x[w] = 0;
         if (__ballot(active)) {
             const int32_t u = active ? gr.col[e0 + k] : r0;
             const uint64_t hm = active ? ~0ull : 0ull;
             // the lane where this row's arcs begin in this step (lanes of one
             // row are consecutive); a lane past the range is its own segment
             const int32_t rs = rstart_off(rk) - base;
-            const int first = in ? (rs > 0 ? rs : 0) : lane;
-            load_words<W>(cur + (size_t)u * W, x);
+            const int first = in ? (rs > 0 ? rs : 0) : al;
+            load_words<WL>(cur + (size_t)u * W + hw, x);
 #pragma unroll
-            for (int w = 0; w < W; w++) x[w] &= hm;
-            seg_or_scan<W>(x, lane, first);
+            for (int w = 0; w < WL; w++) x[w] &= hm;
+            seg_or_scan<WL, AL>(x, al, first);
         }
         // the last lane of a row's run in this step
-        const bool tail = in && (lane == 63 || k + 1 == wb || k + 1 == re);
+        const bool tail = in && (al == AL - 1 || k + 1 == wb || k + 1 == re);
         if (tail && rk == crow) {
 #pragma unroll
-            for (int w = 0; w < W; w++) x[w] |= cacc[w];
+            for (int w = 0; w < WL; w++) x[w] |= sm.wv.cacc[wv][hw + w];
         }
         const bool closes = tail && k + 1 == re;            // the row's last arc in the tile
         const bool leaves = tail && !closes && k + 1 == wb;  // open past this wave's range
-        const bool carries = tail && !closes && !leaves;     // only lane 63
+        const bool carries = tail && !closes && !leaves;     // only the step's last arc
         if (closes) close_row(rk, x);
         else if (leaves) leave_row(rk, x);
-        // carry into the next step; a carried row found complete adds nothing
-        // more, so the wave closes it now and jumps past its remaining arcs
-        if (__builtin_amdgcn_readlane((int)carries, 63)) {
-            crow = __builtin_amdgcn_readlane(rk, 63);
+        // carry into the next step: the carrying lanes (the step's last arc,
+        // one per share of the words) keep the row's OR so far in LDS; a
+        // carried row found complete adds nothing more, so the wave closes it
+        // now and jumps past its remaining arcs
+        if (__builtin_amdgcn_readlane((int)carries, AL - 1)) {
+            crow = __builtin_amdgcn_readlane(rk, AL - 1);
+            bool f = false;
+            if (al == AL - 1) {
 #pragma unroll
-            for (int w = 0; w < W; w++) cacc[w] = readlane64(x[w], 63);
-            {
-                bool f = true;
-#pragma unroll
-                for (int w = 0; w < W; w++) f &= (cacc[w] | ccv[w]) == full[w];
-                if (f) {
-                    const int32_t cre = (int32_t)sm.rend[crow];
-                    if (lane == 0) {
+                for (int w = 0; w < WL; w++) sm.wv.cacc[wv][hw + w] = x[w];
+                f = share_complete<H, WL>(x, ccv, g.full, grp);
+            }
+            if (__builtin_amdgcn_readlane((int)f, AL - 1)) {
+                const int32_t cre = (int32_t)sm.rend[crow];
+                if (al == AL - 1) {
+                    if (h == 0)
                         atomicOr(reinterpret_cast<unsigned long long *>(&sm.fin[crow >> 6]), 1ull << (crow & 63));
-                        if (cre > wb) {
-                            leave_row(crow, cacc);
-                        } else if (rstart_off(crow) >= wa) {
-                            uint64_t cv[W];
+                    if (cre > wb) {
+                        leave_row(crow, x);
+                    } else if (rstart_off(crow) >= wa) {
+                        uint64_t cv[WL];
 #pragma unroll
-                            for (int w = 0; w < W; w++) cv[w] = ccv[w];
-                            finish_row_cv(crow, cacc, cv);
-                        } else {
-                            close_row(crow, cacc);  // pending: merged after the loop
-                        }
+                        for (int w = 0; w < WL; w++) cv[w] = ccv[w];
+                        finish_row_cv(crow, x, cv, hw, grp);
+                    } else {
+                        close_row(crow, x);  // pending: merged after the loop
                     }
-                    next = cre <= wb ? cre : wb;
-                    crow = -1;
                 }
+                next = cre <= wb ? cre : wb;
+                crow = -1;
             }
         } else {
             crow = -1;
@@ -947,36 +1036,40 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         base = next;
     }
     __syncthreads();
-    // rows split between waves: the closing wave's share plus the earlier ones;
-    // the row continuing past the tile merges globally
-    if (threadIdx.x < WAVES) {
-        const int w0 = threadIdx.x;
+    // rows split between waves: the closing wave's share plus the earlier ones
+    // (H threads per wave, one per share of the words); the row continuing
+    // past the tile merges globally (H threads after those)
+    if ((int)threadIdx.x < WAVES * H) {
+        const int w0 = threadIdx.x / H, hx = (threadIdx.x % H) * WL;
+        const uint64_t gx = ((1ull << H) - 1ull) << (w0 * H);
         const int32_t rk = sm.wv.pend_row[w0];
         if (rk >= 0) {
-            uint64_t x[W];
+            uint64_t x[WL];
 #pragma unroll
-            for (int w = 0; w < W; w++) x[w] = sm.wv.pend_acc[w0][w];
+            for (int w = 0; w < WL; w++) x[w] = sm.wv.pend_acc[w0][hx + w];
             for (int w1 = 0; w1 < w0; w1++)
                 if (sm.wv.out_row[w1] == rk) {
 #pragma unroll
-                    for (int w = 0; w < W; w++) x[w] |= sm.wv.out_acc[w1][w];
+                    for (int w = 0; w < WL; w++) x[w] |= sm.wv.out_acc[w1][hx + w];
                 }
-            finish_row(rk, x);
+            finish_row(rk, x, hx, gx);
         }
-    } else if (threadIdx.x == WAVES) {
+    } else if ((int)threadIdx.x < WAVES * H + H) {
+        const int hx = ((int)threadIdx.x - WAVES * H) * WL;
+        const uint64_t gx = ((1ull << H) - 1ull) << (WAVES * H);
         int32_t rk = -1;
         for (int w1 = 0; w1 < WAVES; w1++)
             if (sm.wv.out_row[w1] >= 0 && (int32_t)sm.rend[sm.wv.out_row[w1]] > tile_edges) rk = sm.wv.out_row[w1];
         if (rk >= 0) {
-            uint64_t x[W];
+            uint64_t x[WL];
 #pragma unroll
-            for (int w = 0; w < W; w++) x[w] = 0;
+            for (int w = 0; w < WL; w++) x[w] = 0;
             for (int w1 = 0; w1 < WAVES; w1++)
                 if (sm.wv.out_row[w1] == rk) {
 #pragma unroll
-                    for (int w = 0; w < W; w++) x[w] |= sm.wv.out_acc[w1][w];
+                    for (int w = 0; w < WL; w++) x[w] |= sm.wv.out_acc[w1][hx + w];
                 }
-            finish_row(rk, x);
+            finish_row(rk, x, hx, gx);
         }
     }
     __syncthreads();

@@ -164,12 +164,11 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
     p.minrel = b->encoding == CBFS_ENCODE_MIN ? 1 : 0;
     p.total_sources = b->cluster_ptr[p.C];
     p.WC = (kmax + 63) / 64;
-    // defaults: wide groups share one CSR pass among many clusters (16 words
-    // for clusters of more than 64 sources, 8 for one-word clusters, whose
-    // 16-word pull kernels run at lower occupancy); sparse (high-diameter)
+    // defaults: wide groups share one CSR pass among many clusters (16 words,
+    // which the pull splits over two lanes per vertex); sparse (high-diameter)
     // graphs get narrow groups searched side by side
     const bool sparse = p.m < 8 * p.n;
-    p.W = p.WC == 3 ? 3 : (sparse ? p.WC : (p.WC >= 2 ? 16 : 8));
+    p.W = p.WC == 3 ? 3 : (sparse ? p.WC : 16);
     if (p.W < p.WC) p.W = p.WC;
     p.mode = sparse ? CBFS_MODE_PERSISTENT : CBFS_MODE_HOST_LOOP;
     int32_t want_slots = 0;

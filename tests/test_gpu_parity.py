@@ -75,10 +75,12 @@ TUNINGS = [None, dict(alpha=-1.0), dict(force_pull=1), dict(group_words=1), dict
            dict(gamma=-1.0), dict(mode=1, group_words=16), dict(mode=1, group_words=16, force_pull=1, gamma=1e-9),
            dict(mode=1, hub_arcs=1), dict(mode=1, alpha=-1.0, hub_arcs=1),
            dict(mode=1, alpha=-1.0, hub_arcs=1, group_words=16), dict(mode=1, alpha=-1.0, hub_arcs=1, group_words=1),
-           dict(mode=1, hub_arcs=-1)]
+           dict(mode=1, hub_arcs=-1), dict(mode=2, group_words=16, concurrent_groups=4),
+           dict(mode=2, group_words=16, force_pull=1, gamma=1e-9, concurrent_groups=3)]
 TUNING_IDS = ["default", "push", "pull", "w1", "w8", "host", "host_pull_w2", "host_push", "slots3", "slots64",
               "host_pull_all", "pers_pull_all", "always_test", "w16", "w16_pull_all",
-              "hub", "hub_push_all", "hub_push_all_w16", "hub_push_all_w1", "no_hub"]
+              "hub", "hub_push_all", "hub_push_all_w16", "hub_push_all_w1", "no_hub", "pers_w16",
+              "pers_w16_pull_all"]
 
 
 def tuning_of(t, WC=1):
