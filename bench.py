@@ -64,6 +64,22 @@ def algorithmic_bytes(n, m, stats, C, k_w, R):
     return traversal + own_state + outputs + init
 
 
+def pull_launch_bytes(n, m, stats, C, k_w, R):
+    """Compulsory HBM bytes of one pull launch, averaged over a batch's pull
+    launches: the dense pass (arcs 4m, row pointers 4(n+1), frontier bitmap
+    n/8, every vertex's own state words 8Wn), the vertex phase fused into the
+    launch (24 B per state word of each F_i vertex: own set and seen set read,
+    seen set written, as in the batch model), and the outputs, attributed to
+    pull rounds in proportion of their frontier vertices."""
+    W = stats["group_words"]
+    pulls = max(1, stats["pull_rounds"])
+    fv_pull = stats.get("pull_frontier_vertices", 0)
+    fv = max(1, stats["frontier_vertices"])
+    dense_pass = 4 * m + 4 * (n + 1) + n // 8 + 8 * W * n
+    outputs = C * n * (4 + 8 * k_w * (2 * R + 1))
+    return int(dense_pass + (24 * W * fv_pull + outputs * fv_pull / fv) / pulls)
+
+
 def load_traffic(kind: str, workload: str):
     """Measured HBM bytes per launch from committed rocprofv3 counter runs,
     only if they were taken on the current kernel sources."""
@@ -397,9 +413,10 @@ def main():
         per_launch = B_alg_step * prof_steps / launches
         unit_note = "one batch (all groups) per launch"
     elif kind == "pull":
-        W = stats["group_words"]
-        per_launch = 4 * m + 4 * (n + 1) + n // 8 + 8 * W * n
-        unit_note = "one dense pass over the CSR and the group state per launch"
+        per_launch = pull_launch_bytes(n, m, stats, C, k_w, R)
+        unit_note = ("one dense pass over the CSR, the frontier bitmap and the group state, plus the fused "
+                     "vertex phase of F_i (24 B per state word of each frontier vertex) and its share of the "
+                     "outputs, averaged over the batch's pull launches")
     else:
         per_launch = B_alg_step * prof_steps / launches
         unit_note = "batch bytes spread over the launches"
@@ -427,6 +444,20 @@ def main():
         plain_ms = ev0.elapsed_time(ev1)
         plain = {"value": round(ksum * m / (plain_ms * 1e-3) / 1e9, 2), "ms": round(plain_ms, 2),
                  "calls": C, "batched_speedup": round(plain_ms / step_ms, 2)}
+        # the compulsory bytes of searching every cluster on its own (one
+        # cluster per level loop, as the plain calls do), delivered by the
+        # batch; the per-call frontier counts come from an untimed second pass
+        equiv = 0
+        for ci in range(C):
+            cp1 = np.array([0, cptr[ci + 1] - cptr[ci]], np.int32)
+            P.run_batch(rp_d, col_d, cp1, sources[cptr[ci]:cptr[ci + 1]], R, tuning, out=one, workspace=ws,
+                        stream=stream)
+            equiv += algorithmic_bytes(n, m, P.last_run_stats(), 1, k_w, R)
+        roofline["cluster_equivalent"] = {
+            "bytes": int(equiv), "frac": round(equiv / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "plain_frac": round(equiv / (plain_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "sum over clusters of the batch model's bytes with each cluster in a group of its own, "
+                    "divided by the batch's step time (frac) and by the plain calls' time (plain_frac)"}
         print(f"[bench] plain: {plain}", file=sys.stderr, flush=True)
 
     # CPU oracle on a bounded sample (the first clusters), also checked against the GPU

@@ -313,6 +313,7 @@ typedef struct {
     int64_t frontier_arcs;     /* sum of deg over F_i                         */
     int64_t device_error;
     int64_t persistent_blocks; /* grid of the persistent launch (0 in host-loop mode) */
+    int64_t pull_frontier_vertices; /* sum of |F_i| over the pull rounds           */
 } cbfs_run_stats;
 
 cbfs_status cbfs_last_run_stats(cbfs_run_stats *out);

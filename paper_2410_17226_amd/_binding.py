@@ -63,7 +63,7 @@ class _Trial(ctypes.Structure):
 class _RunStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "groups", "group_words", "slots", "mode", "rounds", "push_rounds", "pull_rounds",
-        "frontier_vertices", "frontier_arcs", "device_error", "persistent_blocks")]
+        "frontier_vertices", "frontier_arcs", "device_error", "persistent_blocks", "pull_frontier_vertices")]
 
 
 class _Labels(ctypes.Structure):

@@ -19,6 +19,10 @@ constexpr int CTL_GEN = 0, CTL_COUNT = 1, CTL_DIE_COUNT = 2, CTL_DIE_TOTAL = 2 +
               CTL_DIE_GEN = 2 + 2 * DIES;
 constexpr int CTL_WORDS = CTL_LINE * (2 + 3 * DIES);
 
+// Per-group statistics the persistent kernel keeps: rounds, push rounds,
+// pull rounds, sum |F_i|, sum deg(F_i), sum |F_i| over pull rounds.
+constexpr int STAT_WORDS = 6;
+
 // Arguments of the persistent batch kernel (all pointers are device memory).
 struct PersistArgs {
     GraphArgs gr;
@@ -31,7 +35,7 @@ struct PersistArgs {
     unsigned int *ctl;          // [CTL_WORDS] barrier state, work counters (zeroed before launch)
     unsigned long long *work;   // [3 * DIES] per-round work counters of each die
     int32_t *err;               // 0 ok, 1 barrier timeout, 2 round limit
-    long long *stats;           // [num_groups][5]: rounds, push, pull, sum |F|, sum deg(F)
+    long long *stats;           // [num_groups][STAT_WORDS]
     float alpha, beta, gamma;
     int32_t force_pull;
     int32_t schedule;           // 0 fixed stride, 1 shared work counter

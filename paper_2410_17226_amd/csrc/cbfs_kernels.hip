@@ -361,11 +361,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
                                                      : (sd.nwords + CLEAR_WORDS - 1) / CLEAR_WORDS);
                     items = wk + clears;
                     if (dix == 0) {
-                        long long *st = a.stats + 5 * (int64_t)group_of(sl_me);
+                        long long *st = a.stats + STAT_WORDS * (int64_t)group_of(sl_me);
                         st[0] += 1;
                         st[dense ? 2 : 1] += 1;
                         st[3] += verts;
                         st[4] += degsum;
+                        if (dense) st[5] += verts;
                     }
                 }
                 if (verts == 0) s_done[sl_me] = 1;

@@ -41,7 +41,7 @@ struct LastRun {
     bool valid = false;
     bool device_stats = false;
     hipStream_t stream = nullptr;
-    const long long *stats = nullptr;  // device [groups][5] (persistent mode)
+    const long long *stats = nullptr;  // device [groups][STAT_WORDS] (persistent mode)
     const int32_t *err = nullptr;      // device error flag (persistent mode)
     cbfs_run_stats host{};
 };
@@ -226,7 +226,7 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
     p.off_slotdesc = take(sizeof(SlotArgs) * MAX_SLOTS);
     p.off_groupdesc = take(sizeof(GroupDesc) * (size_t)p.groups);
     p.off_ctl = take(sizeof(unsigned int) * CTL_WORDS + 512);
-    p.off_stats = take(sizeof(long long) * 5 * (size_t)p.groups);
+    p.off_stats = take(sizeof(long long) * STAT_WORDS * (size_t)p.groups);
     p.off_hub = take(sizeof(int32_t) * (HUB_MAX + 1));
     p.off_slots = off;
     size_t sb = 0;
@@ -439,6 +439,7 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
             (dense ? rs.pull_rounds : rs.push_rounds)++;
             rs.frontier_vertices += verts;
             rs.frontier_arcs += degsum;
+            if (dense) rs.pull_frontier_vertices += verts;
             // the group's first dense round, with a frontier carrying most of
             // the arcs: few rows can be complete yet, and the wave form gathers
             // every neighbour's set (the sets of non-members add nothing new,
@@ -499,7 +500,8 @@ static cbfs_status run_persistent(const Plan &p, const cbfs_csr *g, uint32_t *di
     // path is never captured into a graph)
     if ((e = hipMemsetAsync(ws + p.off_ctl, 0, sizeof(unsigned int) * CTL_WORDS + 512, st)) != hipSuccess)
         return hip_fail("control reset", e);
-    if ((e = hipMemsetAsync(ws + p.off_stats, 0, sizeof(long long) * 5 * (size_t)p.groups, st)) != hipSuccess)
+    if ((e = hipMemsetAsync(ws + p.off_stats, 0, sizeof(long long) * STAT_WORDS * (size_t)p.groups, st)) !=
+        hipSuccess)
         return hip_fail("stats reset", e);
     if ((e = PROF(CBFS_KERNEL_PERSISTENT, st, launch_persistent(p.W, p.WC, a, blocks, st))) != hipSuccess)
         return hip_fail("persistent launch", e);
@@ -692,7 +694,7 @@ extern "C" cbfs_status cbfs_last_run_stats(cbfs_run_stats *out)
     if (!g_last.valid) return fail(CBFS_E_ARG, "cbfs_last_run_stats: no cbfs_run_batch call on this thread");
     cbfs_run_stats r = g_last.host;
     if (g_last.device_stats) {
-        std::vector<long long> st(5 * (size_t)r.groups);
+        std::vector<long long> st(STAT_WORDS * (size_t)r.groups);
         int32_t err = 0;
         hipError_t e;
         if ((e = hipStreamSynchronize(g_last.stream)) != hipSuccess) return hip_fail("stats sync", e);
@@ -702,11 +704,13 @@ extern "C" cbfs_status cbfs_last_run_stats(cbfs_run_stats *out)
         if ((e = hipMemcpy(&err, g_last.err, sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess)
             return hip_fail("error flag copy", e);
         for (int64_t grp = 0; grp < r.groups; grp++) {
-            r.rounds += st[5 * grp + 0];
-            r.push_rounds += st[5 * grp + 1];
-            r.pull_rounds += st[5 * grp + 2];
-            r.frontier_vertices += st[5 * grp + 3];
-            r.frontier_arcs += st[5 * grp + 4];
+            const long long *sg = st.data() + STAT_WORDS * grp;
+            r.rounds += sg[0];
+            r.push_rounds += sg[1];
+            r.pull_rounds += sg[2];
+            r.frontier_vertices += sg[3];
+            r.frontier_arcs += sg[4];
+            r.pull_frontier_vertices += sg[5];
         }
         r.device_error = err;
     }
