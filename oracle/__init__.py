@@ -17,6 +17,9 @@ product package, and the product package never imports it.
                          ground truth landmark answers bound from above.
 * ``local_search``    -- the query path's bidirectional local search
                          (Appendix B), tau vertices from each endpoint.
+* ``pll``, ``pll_query`` -- exact 2-hop labels by pruned BFS in batches of
+                         growing size (the exact distance oracle), and
+                         their query.
 * ``query_labels``    -- the same query from encoded labels by the lowest
                          non-empty intersection (Section 4.2).
 * ``certificate``     -- BFS-distance certificate of any encoded output.
@@ -75,6 +78,10 @@ def _load():
         lib.oracle_pair_distances.restype = ctypes.c_int
         lib.oracle_local_search.argtypes = [i64, P, P, i64, P, P, i32, P, i32]
         lib.oracle_local_search.restype = ctypes.c_int
+        lib.oracle_pll.argtypes = [i64, P, P, i32, i32, P, P, i64, P, i32, ctypes.c_double, i32, i32, P, P, i32]
+        lib.oracle_pll.restype = ctypes.c_int
+        lib.oracle_pll_query.argtypes = [i64, i32, i32, P, P, i32, P, P, i64, P, P, P]
+        lib.oracle_pll_query.restype = ctypes.c_int
         lib.oracle_query_labels.argtypes = [i64, i32, i32, P, P, i64, P, P, P]
         lib.oracle_query_labels.restype = ctypes.c_int
         lib.oracle_certificate.argtypes = [i64, P, P, i32, P, i32, i32, P, P, i32]
@@ -201,6 +208,66 @@ def local_search(row_ptr, col, qs, qt, tau: int, nthreads: int = 0) -> np.ndarra
                                      int(nthreads))
     if rc != 0:
         raise ValueError(f"oracle_local_search failed: {rc}")
+    return out
+
+
+def _bp(bp):
+    """Phase-1 labels (dist [C][n], masks [C][2R+1][n][1]) as C arrays, or none."""
+    if bp is None:
+        return 0, 0, np.zeros(1, np.uint32), np.zeros(1, np.uint64)
+    dist, masks = bp
+    dist = np.ascontiguousarray(dist, dtype=np.uint32)
+    masks = np.ascontiguousarray(masks, dtype=np.uint64)
+    C, Pl, n, W = masks.shape
+    if W != 1:
+        raise ValueError("phase-1 labels need one mask word per vertex")
+    return C, (Pl - 1) // 2, dist, masks
+
+
+def pll(row_ptr, col, order, bp=None, first: int = 200, growth: float = 1.5, max_batch: int = 1000,
+        label_cap: int = 256, nthreads: int = 0):
+    """Exact 2-hop labels by pruned BFS in batches (the exact distance oracle's
+    phase 2): returns (counts int32[n], labels uint64[n][label_cap]), each
+    entry (rank << 32) | distance, sorted by rank.  ``bp`` = phase-1 cluster
+    labels (dist, masks) or None."""
+    row_ptr, col, n = _csr(row_ptr, col)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    C, R, bd, bm = _bp(bp)
+    cnt = np.zeros(n, dtype=np.int32)
+    labels = np.zeros((n, label_cap), dtype=np.uint64)
+    rc = _load().oracle_pll(n, _p(row_ptr), _p(col), C, R, _p(bd), _p(bm), order.size, _p(order), int(first),
+                            float(growth), int(max_batch), int(label_cap), _p(cnt), _p(labels), int(nthreads))
+    if rc == -9:
+        raise OverflowError("oracle_pll: a label exceeded label_cap")
+    if rc != 0:
+        raise ValueError(f"oracle_pll failed: {rc}")
+    return cnt, labels
+
+
+def pll_query(cnt, labels, qs, qt, bp=None) -> np.ndarray:
+    """Exact-oracle query: min of the phase-1 answer and the 2-hop label answer."""
+    cnt = np.ascontiguousarray(cnt, dtype=np.int32)
+    labels = np.ascontiguousarray(labels, dtype=np.uint64)
+    n, cap = labels.shape
+    C, R, bd, bm = _bp(bp)
+    qs = np.ascontiguousarray(qs, dtype=np.int32)
+    qt = np.ascontiguousarray(qt, dtype=np.int32)
+    ans = np.empty(qs.size, dtype=np.uint32)
+    rc = _load().oracle_pll_query(n, C, R, _p(bd), _p(bm), cap, _p(cnt), _p(labels), qs.size, _p(qs), _p(qt),
+                                  _p(ans))
+    if rc != 0:
+        raise ValueError(f"oracle_pll_query failed: {rc}")
+    return ans
+
+
+def pll_batches(count: int, first: int = 200, growth: float = 1.5, max_batch: int = 1000):
+    """The batch sizes the exact oracle's phase 2 uses for ``count`` roots."""
+    out, b, lo = [], int(first), 0
+    while lo < count:
+        size = min(b, count - lo)
+        out.append(size)
+        lo += size
+        b = max(1, min(int(max_batch), int(b * growth)))
     return out
 
 

@@ -51,6 +51,7 @@
 #define OR_E_ARG (-1)
 #define OR_E_RADIUS (-5)
 #define OR_E_NOMEM (-8)
+#define OR_E_CAPACITY (-9)
 #define UNREACHED (-1)
 
 #define MAX_THREADS 256
@@ -551,32 +552,270 @@ int oracle_local_search(int64_t n, const int32_t *row_ptr, const int32_t *col, i
  * per cluster, scan offset pairs (a, b) in increasing order of a + b and stop at
  * the first non-empty intersection mask[a][s] & mask[b][t]; the candidate is
  * dist[s] + dist[t] + a + b.  The answer is the minimum over clusters. */
+/* Landmark-label answer for one pair from cluster-major encoded labels:
+ * per cluster the lowest offset sum whose subsets at s and t intersect. */
+static uint32_t label_pair(int64_t n, int32_t num_clusters, int32_t R, const uint32_t *dist,
+                           const uint64_t *masks, int32_t s, int32_t t)
+{
+    const int64_t P = 2 * (int64_t)R + 1;
+    uint32_t best = UINT32_MAX;
+    for (int32_t c = 0; c < num_clusters; c++) {
+        const uint32_t ds = dist[(size_t)c * n + s], dt = dist[(size_t)c * n + t];
+        if (ds == UINT32_MAX || dt == UINT32_MAX) continue;
+        const uint64_t *mc = masks + (size_t)c * (size_t)P * (size_t)n;
+        int found = 0;
+        for (int32_t sum = -2 * R; sum <= 2 * R && !found; sum++) {
+            for (int32_t a = -R; a <= R; a++) {
+                int32_t b = sum - a;
+                if (b < -R || b > R) continue;
+                if (mc[(size_t)(a + R) * n + s] & mc[(size_t)(b + R) * n + t]) {
+                    int64_t val = (int64_t)ds + (int64_t)dt + sum;
+                    if ((uint64_t)val < best) best = (uint32_t)val;
+                    found = 1;
+                    break;
+                }
+            }
+        }
+    }
+    return best;
+}
+
 int oracle_query_labels(int64_t n, int32_t num_clusters, int32_t R, const uint32_t *dist,
                         const uint64_t *masks, int64_t q, const int32_t *qs, const int32_t *qt,
                         uint32_t *ans)
 {
     if (n <= 0 || R < 0 || q < 0) return OR_E_ARG;
-    const int64_t P = 2 * (int64_t)R + 1;
     for (int64_t p = 0; p < q; p++) {
         const int32_t s = qs[p], t = qt[p];
         if (s < 0 || s >= n || t < 0 || t >= n) return OR_E_ARG;
-        uint32_t best = UINT32_MAX;
-        for (int32_t c = 0; c < num_clusters; c++) {
-            const uint32_t ds = dist[(size_t)c * n + s], dt = dist[(size_t)c * n + t];
-            if (ds == UINT32_MAX || dt == UINT32_MAX) continue;
-            const uint64_t *mc = masks + (size_t)c * (size_t)P * (size_t)n;
-            int found = 0;
-            for (int32_t sum = -2 * R; sum <= 2 * R && !found; sum++) {
-                for (int32_t a = -R; a <= R; a++) {
-                    int32_t b = sum - a;
-                    if (b < -R || b > R) continue;
-                    if (mc[(size_t)(a + R) * n + s] & mc[(size_t)(b + R) * n + t]) {
-                        int64_t val = (int64_t)ds + (int64_t)dt + sum;
-                        if ((uint64_t)val < best) best = (uint32_t)val;
-                        found = 1;
-                        break;
-                    }
+        ans[p] = label_pair(n, num_clusters, R, dist, masks, s, t);
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Exact 2-hop labels by pruned BFS (the exact distance oracle of the paper's
+ * appendix: pruned landmark labeling, phase 2, run in batches of growing
+ * size).
+ *
+ * Roots are taken in rank order (order[0] first).  Batch i holds the next
+ * b_i roots, b_0 = first, b_{i+1} = min(max_batch, floor(b_i * growth)).  Each
+ * root h of a batch runs a FIFO BFS; at a vertex u reached at distance d it
+ * asks the index as it stood when the batch began: the phase-1 cluster labels
+ * (the landmark query over every cluster) and the pairs (r, d_r) already in
+ * the labels of both h and u.  If that answer is at most d, u is pruned: it
+ * gets no label and is not expanded.  Otherwise (rank(h), d) joins u's label
+ * and u's neighbours are visited.  Labels added in a batch become visible to
+ * the next batch.  Each vertex's label ends sorted by rank; an entry is
+ * (rank << 32) | distance.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;
+    const int32_t *row_ptr, *col;
+    int32_t num_clusters, R;
+    const uint32_t *bp_dist;
+    const uint64_t *bp_masks;
+    const int32_t *order;
+    int64_t lo_rank;
+    int32_t label_cap;
+    const int32_t *cnt0;      /* label sizes when the batch began */
+    const uint64_t *labels;   /* [n][label_cap] */
+    int32_t *dist;            /* [nthreads][n], -1 */
+    int32_t *queue;           /* [nthreads][n] */
+    uint32_t *root_map;       /* [nthreads][count]: distance of the root to a rank, UINT32_MAX if none */
+    uint64_t **out;           /* [nthreads] growable: labelled vertex of each new entry */
+    int64_t *out_len, *out_cap;
+    uint64_t **out_e;         /* [nthreads] the new entries, (rank << 32) | distance */
+    int failed;
+} pll_ctx;
+
+static int pll_push(pll_ctx *c, int tid, int32_t v, uint64_t entry)
+{
+    if (c->out_len[tid] == c->out_cap[tid]) {
+        int64_t cap = c->out_cap[tid] ? 2 * c->out_cap[tid] : 1024;
+        uint64_t *a = (uint64_t *)realloc(c->out[tid], sizeof(uint64_t) * (size_t)cap);
+        uint64_t *b = (uint64_t *)realloc(c->out_e[tid], sizeof(uint64_t) * (size_t)cap);
+        if (!a || !b) {
+            if (a) c->out[tid] = a;
+            if (b) c->out_e[tid] = b;
+            return -1;
+        }
+        c->out[tid] = a;
+        c->out_e[tid] = b;
+        c->out_cap[tid] = cap;
+    }
+    c->out[tid][c->out_len[tid]] = (uint64_t)(uint32_t)v;
+    c->out_e[tid][c->out_len[tid]] = entry;
+    c->out_len[tid]++;
+    return 0;
+}
+
+static void pll_body(int64_t lo, int64_t hi, int tid, void *p)
+{
+    pll_ctx *c = (pll_ctx *)p;
+    const int64_t n = c->n;
+    int32_t *dist = c->dist + (size_t)tid * n;
+    int32_t *queue = c->queue + (size_t)tid * n;
+    uint32_t *rmap = c->root_map + (size_t)tid * n;
+    for (int64_t j = lo; j < hi; j++) {
+        const int64_t rank = c->lo_rank + j;
+        const int32_t h = c->order[rank];
+        const uint64_t *lh = c->labels + (size_t)h * c->label_cap;
+        for (int32_t e = 0; e < c->cnt0[h]; e++) rmap[lh[e] >> 32] = (uint32_t)lh[e];
+        int64_t head = 0, tail = 0;
+        queue[tail++] = h;
+        dist[h] = 0;
+        while (head < tail) {
+            const int32_t u = queue[head++];
+            const int32_t d = dist[u];
+            /* the index's answer for (h, u) */
+            uint32_t q = c->num_clusters ? label_pair(n, c->num_clusters, c->R, c->bp_dist, c->bp_masks, h, u)
+                                         : UINT32_MAX;
+            const uint64_t *lu = c->labels + (size_t)u * c->label_cap;
+            for (int32_t e = 0; e < c->cnt0[u]; e++) {
+                const uint32_t dh = rmap[lu[e] >> 32];
+                if (dh == UINT32_MAX) continue;
+                const uint64_t sum = (uint64_t)dh + (uint32_t)lu[e];
+                if (sum < q) q = (uint32_t)sum;
+            }
+            if (q <= (uint32_t)d) continue; /* pruned */
+            if (pll_push(c, tid, u, ((uint64_t)rank << 32) | (uint32_t)d) != 0) {
+                c->failed = OR_E_NOMEM;
+                break;
+            }
+            for (int32_t a = c->row_ptr[u]; a < c->row_ptr[u + 1]; a++) {
+                const int32_t w = c->col[a];
+                if (dist[w] == UNREACHED) {
+                    dist[w] = d + 1;
+                    queue[tail++] = w;
                 }
+            }
+        }
+        for (int64_t k = 0; k < tail; k++) dist[queue[k]] = UNREACHED;
+        for (int32_t e = 0; e < c->cnt0[h]; e++) rmap[lh[e] >> 32] = UINT32_MAX;
+    }
+}
+
+static int cmp_u64(const void *a, const void *b)
+{
+    const uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+int oracle_pll(int64_t n, const int32_t *row_ptr, const int32_t *col, int32_t num_clusters, int32_t R,
+               const uint32_t *bp_dist, const uint64_t *bp_masks, int64_t count, const int32_t *order,
+               int32_t first, double growth, int32_t max_batch, int32_t label_cap, int32_t *lab_cnt,
+               uint64_t *labels, int32_t nthreads)
+{
+    if (n <= 0 || count < 0 || count > n || num_clusters < 0 || R < 0 || first < 1 || !(growth >= 1.0) ||
+        max_batch < 1 || label_cap < 1 || (num_clusters > 0 && (!bp_dist || !bp_masks)))
+        return OR_E_ARG;
+    for (int64_t k = 0; k < count; k++)
+        if (order[k] < 0 || order[k] >= n) return OR_E_ARG;
+    int nt = nthreads_or_default(nthreads);
+    int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * nt);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * nt);
+    uint32_t *rmap = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n * nt);
+    int32_t *cnt0 = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    uint64_t **out = (uint64_t **)calloc((size_t)nt, sizeof(uint64_t *));
+    uint64_t **out_e = (uint64_t **)calloc((size_t)nt, sizeof(uint64_t *));
+    int64_t *out_len = (int64_t *)calloc((size_t)nt, sizeof(int64_t));
+    int64_t *out_cap = (int64_t *)calloc((size_t)nt, sizeof(int64_t));
+    int rc = OR_OK;
+    if (!dist || !queue || !rmap || !cnt0 || !out || !out_e || !out_len || !out_cap) {
+        rc = OR_E_NOMEM;
+        goto done;
+    }
+    for (size_t k = 0; k < (size_t)n * nt; k++) {
+        dist[k] = UNREACHED;
+        rmap[k] = UINT32_MAX;
+    }
+    for (int64_t v = 0; v < n; v++) lab_cnt[v] = 0;
+    pll_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.n = n;
+    c.row_ptr = row_ptr;
+    c.col = col;
+    c.num_clusters = num_clusters;
+    c.R = R;
+    c.bp_dist = bp_dist;
+    c.bp_masks = bp_masks;
+    c.order = order;
+    c.label_cap = label_cap;
+    c.cnt0 = cnt0;
+    c.labels = labels;
+    c.dist = dist;
+    c.queue = queue;
+    c.root_map = rmap;
+    c.out = out;
+    c.out_e = out_e;
+    c.out_len = out_len;
+    c.out_cap = out_cap;
+    int64_t b = first;
+    for (int64_t lo = 0; lo < count;) {
+        const int64_t size = b < count - lo ? b : count - lo;
+        memcpy(cnt0, lab_cnt, sizeof(int32_t) * (size_t)n);
+        c.lo_rank = lo;
+        for (int t = 0; t < nt; t++) out_len[t] = 0;
+        parallel_for(size, 1, nt, pll_body, &c);
+        if (c.failed) {
+            rc = c.failed;
+            goto done;
+        }
+        for (int t = 0; t < nt; t++)
+            for (int64_t k = 0; k < out_len[t]; k++) {
+                const int32_t v = (int32_t)out[t][k];
+                if (lab_cnt[v] >= label_cap) {
+                    rc = OR_E_CAPACITY;
+                    goto done;
+                }
+                labels[(size_t)v * label_cap + lab_cnt[v]++] = out_e[t][k];
+            }
+        lo += size;
+        int64_t nb = (int64_t)((double)b * growth);
+        b = nb < max_batch ? nb : max_batch;
+        if (b < 1) b = 1;
+    }
+    for (int64_t v = 0; v < n; v++) qsort(labels + (size_t)v * label_cap, (size_t)lab_cnt[v], sizeof(uint64_t), cmp_u64);
+done:
+    if (out)
+        for (int t = 0; t < nt; t++) free(out[t]);
+    if (out_e)
+        for (int t = 0; t < nt; t++) free(out_e[t]);
+    free(out);
+    free(out_e);
+    free(out_len);
+    free(out_cap);
+    free(dist);
+    free(queue);
+    free(rmap);
+    free(cnt0);
+    return rc;
+}
+
+/* Query of the exact oracle: the lowest of the phase-1 landmark answer and
+ * min over ranks in both labels of the two distances' sum (labels sorted by
+ * rank, merged). */
+int oracle_pll_query(int64_t n, int32_t num_clusters, int32_t R, const uint32_t *bp_dist,
+                     const uint64_t *bp_masks, int32_t label_cap, const int32_t *lab_cnt, const uint64_t *labels,
+                     int64_t q, const int32_t *qs, const int32_t *qt, uint32_t *ans)
+{
+    if (n <= 0 || num_clusters < 0 || R < 0 || label_cap < 1 || q < 0) return OR_E_ARG;
+    for (int64_t p = 0; p < q; p++) {
+        const int32_t s = qs[p], t = qt[p];
+        if (s < 0 || s >= n || t < 0 || t >= n) return OR_E_ARG;
+        uint32_t best = num_clusters ? label_pair(n, num_clusters, R, bp_dist, bp_masks, s, t) : UINT32_MAX;
+        const uint64_t *ls = labels + (size_t)s * label_cap, *lt = labels + (size_t)t * label_cap;
+        int32_t i = 0, j = 0;
+        while (i < lab_cnt[s] && j < lab_cnt[t]) {
+            const uint64_t rs = ls[i] >> 32, rt = lt[j] >> 32;
+            if (rs < rt) i++;
+            else if (rt < rs) j++;
+            else {
+                const uint64_t sum = (uint64_t)(uint32_t)ls[i] + (uint32_t)lt[j];
+                if (sum < best) best = (uint32_t)sum;
+                i++;
+                j++;
             }
         }
         ans[p] = best;

@@ -747,3 +747,99 @@ def test_landmark_selection_rule(seed):
             assert sub.max() <= dd
             marked[cl] = True
         assert marked.all()  # 1000 clusters exhaust the graph
+
+
+# ---------------------------------------------------------------------------
+# Exact distance oracle: pruned landmark labeling in batches (phase 2)
+# ---------------------------------------------------------------------------
+def pll_case(name, g, with_bp):
+    n, s, d = g
+    rp, col, _ = oracle.clean_csr(n, s, d, flags=7)
+    nv = rp.size - 1
+    bp, sources = None, np.zeros(0, np.int32)
+    if with_bp:
+        cp, sources = oracle.select_landmarks(rp, col, 2, 8, 2)
+        dist, masks, st = oracle.cbfs(rp, col, cp, sources, R=1)
+        assert (st == 0).all()
+        bp = (dist, masks)
+    deg = np.diff(rp)
+    order = np.lexsort((np.arange(nv), -deg)).astype(np.int32)
+    order = order[~np.isin(order, sources)]
+    return rp, col, nv, bp, sources, order
+
+
+def pll_expected(D, order, sources, batches):
+    """Labels from the characterisation of batched pruned BFS: root h of batch
+    b labels v with d(h, v) iff no vertex of an earlier batch (phase-1 sources
+    count as earliest) lies on a shortest h-v path."""
+    n = D.shape[0]
+    batch_of = np.full(n, np.iinfo(np.int64).max)
+    batch_of[sources] = -1
+    lo = 0
+    for i, size in enumerate(batches):
+        batch_of[order[lo:lo + size]] = i
+        lo += size
+    rank_of = np.full(n, -1)
+    rank_of[order] = np.arange(order.size)
+    labels = [set() for _ in range(n)]
+    for h in order:
+        b = batch_of[h]
+        E = np.nonzero(batch_of < b)[0]
+        dh = D[h]
+        reach = dh >= 0
+        pruned = np.zeros(n, bool)
+        if E.size:
+            dhE = D[h, E][:, None]
+            dEv = D[E, :]
+            ok = (dhE >= 0) & (dEv >= 0)
+            pruned = ((dhE + dEv == dh[None, :]) & ok).any(axis=0)
+        for v in np.nonzero(reach & ~pruned)[0]:
+            labels[v].add((int(rank_of[h]), int(dh[v])))
+    return labels
+
+
+def pll_as_sets(cnt, lab):
+    return [set((int(e) >> 32, int(e) & 0xFFFFFFFF) for e in lab[v, :cnt[v]]) for v in range(cnt.size)]
+
+
+PLL_GRAPHS = [("gnp", synth.random_graph(70, 0.06, 3)), ("tree", synth.random_tree(60, 4)),
+              ("grid", synth.grid_edges(8, 0.2, seed=2)), ("gnp_disconnected", synth.random_graph(80, 0.02, 9))]
+PLL_SCHEDULES = [(1, 1.0, 1), (3, 1.5, 7), (200, 1.5, 1000)]
+
+
+@pytest.mark.parametrize("name,g", PLL_GRAPHS)
+@pytest.mark.parametrize("with_bp", [False, True])
+@pytest.mark.parametrize("sched", PLL_SCHEDULES)
+def test_pll_labels_match_characterisation_and_cover(name, g, with_bp, sched):
+    """Pruned landmark labeling in batches against (a) the set of labels its
+    pruning rule implies, evaluated by brute force on all-pairs distances (batch
+    size 1 is the canonical labeling of the sequential method), and (b) the
+    2-hop cover property: every query answer is the exact distance."""
+    rp, col, nv, bp, sources, order = pll_case(name, g, with_bp)
+    first, growth, mx = sched
+    cnt, lab = oracle.pll(rp, col, order, bp=bp, first=first, growth=growth, max_batch=mx, label_cap=nv, nthreads=3)
+    D = apsp(rp, col)
+    want = pll_expected(D, order, sources, oracle.pll_batches(order.size, first, growth, mx))
+    got = pll_as_sets(cnt, lab)
+    for v in range(nv):
+        assert got[v] == want[v], (v, sorted(got[v] ^ want[v])[:5])
+        assert np.all(np.diff(lab[v, :cnt[v]].astype(np.uint64) >> np.uint64(32)) > 0)  # sorted by rank
+    qs, qt = np.meshgrid(np.arange(nv, dtype=np.int32), np.arange(nv, dtype=np.int32))
+    ans = oracle.pll_query(cnt, lab, qs.ravel(), qt.ravel(), bp=bp).astype(np.int64)
+    ref = D[qs.ravel(), qt.ravel()]
+    assert np.array_equal(ans[ref >= 0], ref[ref >= 0])
+    assert (ans[ref < 0] == 0xFFFFFFFF).all()
+
+
+def test_pll_batches_and_capacity():
+    assert oracle.pll_batches(5000) == [200, 300, 450, 675, 1000, 1000, 1000, 375]
+    assert oracle.pll_batches(3, 1, 1.0, 1) == [1, 1, 1]
+    n, s, d = synth.random_graph(60, 0.1, 1)
+    rp, col, _ = oracle.clean_csr(n, s, d, flags=7)
+    order = np.arange(rp.size - 1, dtype=np.int32)
+    with pytest.raises(OverflowError):
+        oracle.pll(rp, col, order, label_cap=2)
+    # batches change which labels exist, never the answers
+    a = oracle.pll(rp, col, order, first=1, growth=1.0, max_batch=1, label_cap=64)
+    b = oracle.pll(rp, col, order, label_cap=64)
+    assert (a[0] <= b[0]).all() and a[0].sum() < b[0].sum()
