@@ -329,7 +329,8 @@ enum {
     CBFS_KERNEL_LABELS = 7,
     CBFS_KERNEL_QUERY = 8,
     CBFS_KERNEL_LOCAL = 9,
-    CBFS_KERNEL_KINDS = 10
+    CBFS_KERNEL_PLL = 10,
+    CBFS_KERNEL_KINDS = 11
 };
 cbfs_status cbfs_profile_enable(int32_t enable);
 cbfs_status cbfs_profile_read(int64_t *launches, double *total_ms);
@@ -430,6 +431,59 @@ cbfs_status cbfs_query_batch(const cbfs_labels *L, int64_t q, const int32_t *s, 
 #define CBFS_LOCAL_TAU_MAX 2048
 cbfs_status cbfs_query_local(const cbfs_csr *g, int64_t q, const int32_t *s, const int32_t *t, int32_t tau,
                              uint32_t *ans, void *stream);
+
+/* ------------------------------------------------------------------------ *
+ * Exact 2-hop distance oracle (the paper's appendix on the exact distance
+ * oracle: pruned landmark labeling, whose phase 1 is a C-BFS batch and whose
+ * phase 2 runs a pruned BFS from every remaining vertex, in batches of growing
+ * size searched side by side).
+ *
+ * Phase 1: the center-relative labels of a C-BFS batch (cbfs_run_batch, then
+ * cbfs_labels_pack), passed as bp; they answer the shortest path through any
+ * of the batch's sources.  bp may be NULL (no phase 1).
+ *
+ * cbfs_pll_build: phase 2.  order (device [count]) lists the roots by rank
+ * (rank k = order[k]); the phase-1 sources need not be listed (the index
+ * already covers every pair through them, so they would add nothing).  Batch i
+ * holds the next b_i roots: b_0 = first, b_{i+1} = min(max_batch,
+ * floor(b_i * growth)).  Root h of a batch runs a BFS; at vertex u, reached at
+ * distance d, the index as it stood when the batch began answers (h, u) (the
+ * phase-1 labels, and the ranks r with (r, d_hr) in the label of h and
+ * (r, d_ur) in the label of u: d_hr + d_ur); an answer at most d prunes u (no
+ * label, not expanded), else (rank(h), d) joins u's label and u's neighbours
+ * are visited.  Labels added in a batch are seen from the next batch on, so
+ * the result does not depend on how the device runs a batch.
+ * Outputs (device, caller-owned): lab_cnt [n] and labels [n][label_cap], the
+ * entries of vertex v being labels[v][0 .. lab_cnt[v]) = (rank << 32) |
+ * distance, sorted by rank.  1 <= label_cap <= CBFS_PLL_LABEL_CAP_MAX.
+ * Workspace: cbfs_pll_workspace_size(n, params) bytes (per search slot a
+ * visited bitmap and two frontier queues of n entries).  The call waits for
+ * the stream at its end, to read the overflow flag.
+ * Errors: CBFS_E_ARG; CBFS_E_WORKSPACE (workspace too small, or a vertex's
+ * label would exceed label_cap: the outputs are then incomplete); CBFS_E_HIP.
+ *
+ * cbfs_pll_query: ans[j] = the lower of the phase-1 answer (bp, may be NULL)
+ * and min over ranks in both labels of the two distances' sum, for device
+ * arrays s, t of length q; exact when the labels come from cbfs_pll_build over
+ * all non-source vertices.  CBFS_UNREACHED when nothing covers the pair.
+ * ------------------------------------------------------------------------ */
+#define CBFS_PLL_LABEL_CAP_MAX 4096
+#define CBFS_PLL_PHASE1_WORDS_MAX 2048 /* phase-1 mask words per vertex (clusters x 2R) */
+typedef struct {
+    int32_t first;     /* roots in the first batch: 0 = 200                          */
+    float growth;      /* batch growth factor (>= 1): 0 = 1.5                          */
+    int32_t max_batch; /* largest batch: 0 = 1000                                      */
+    int32_t slots;     /* roots searched at once (a batch runs in chunks of this many):
+                          0 = min(max_batch, 1024)                                     */
+} cbfs_pll_params;
+
+size_t cbfs_pll_workspace_size(int64_t n, const cbfs_pll_params *params);
+cbfs_status cbfs_pll_build(const cbfs_csr *g, const cbfs_labels *bp, const int32_t *order, int64_t count,
+                           const cbfs_pll_params *params, int32_t label_cap, int32_t *lab_cnt, uint64_t *labels,
+                           void *workspace, size_t workspace_bytes, void *stream);
+cbfs_status cbfs_pll_query(const cbfs_labels *bp, int64_t n, int32_t label_cap, const int32_t *lab_cnt,
+                           const uint64_t *labels, int64_t q, const int32_t *s, const int32_t *t, uint32_t *ans,
+                           void *stream);
 
 #ifdef __cplusplus
 }

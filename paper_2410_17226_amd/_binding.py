@@ -26,8 +26,9 @@ SYMBOLS = [
     "cbfs_last_run_stats", "cbfs_profile_enable", "cbfs_profile_read",
     "cbfs_labels_pack", "cbfs_query_batch", "cbfs_autotune_workspace_size", "cbfs_autotune",
     "cbfs_release", "cbfs_run_batch_static", "cbfs_select_landmarks", "cbfs_query_local",
+    "cbfs_pll_workspace_size", "cbfs_pll_build", "cbfs_pll_query",
 ]
-KERNEL_KINDS = ["tiles", "init", "seed", "push", "pull", "finalize", "persistent", "labels", "query", "local"]
+KERNEL_KINDS = ["tiles", "init", "seed", "push", "pull", "finalize", "persistent", "labels", "query", "local", "pll"]
 
 _lib = None
 
@@ -136,6 +137,12 @@ def load():
     lib.cbfs_labels_pack.restype = i32
     lib.cbfs_query_batch.argtypes = [P, i64, P, P, P, P]
     lib.cbfs_query_batch.restype = i32
+    lib.cbfs_pll_workspace_size.argtypes = [i64, P]
+    lib.cbfs_pll_workspace_size.restype = sz
+    lib.cbfs_pll_build.argtypes = [P, P, P, i64, P, i32, P, P, P, sz, P]
+    lib.cbfs_pll_build.restype = i32
+    lib.cbfs_pll_query.argtypes = [P, i64, i32, P, P, i64, P, P, P, P]
+    lib.cbfs_pll_query.restype = i32
     lib.cbfs_query_local.argtypes = [P, i64, P, P, i32, P, P]
     lib.cbfs_query_local.restype = i32
     lib.cbfs_autotune_workspace_size.argtypes = [P, P, i32]
@@ -391,6 +398,52 @@ def labels_pack(dist, masks, R: int, stream=None):
 
 
 LOCAL_TAU_MAX = 2048
+PLL_LABEL_CAP_MAX = 4096
+
+
+class _PllParams(ctypes.Structure):
+    _fields_ = [("first", ctypes.c_int32), ("growth", ctypes.c_float), ("max_batch", ctypes.c_int32),
+                ("slots", ctypes.c_int32)]
+
+
+def pll_build(row_ptr, col, order, bp=None, label_cap: int = 256, first: int = 0, growth: float = 0.0,
+              max_batch: int = 0, slots: int = 0, stream=None):
+    """``cbfs_pll_build`` on device CSR tensors; ``order`` a device int32 tensor
+    of roots by rank; ``bp`` = (dist_vm, mask_vm, R) phase-1 labels or None.
+    Returns (lab_cnt int32[n], labels int64[n][label_cap]) on the device."""
+    torch = _torch()
+    n = row_ptr.numel() - 1
+    params = _PllParams(int(first), float(growth), int(max_batch), int(slots))
+    ws_bytes = load().cbfs_pll_workspace_size(n, ctypes.byref(params))
+    if ws_bytes == 0:
+        raise CbfsError(-1, "cbfs_pll_workspace_size", "bad batch parameters")
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=row_ptr.device)
+    cnt = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+    labels = torch.empty((n, int(label_cap)), dtype=torch.int64, device=row_ptr.device)
+    g = _Csr(n, col.numel(), row_ptr.data_ptr(), col.data_ptr())
+    L = None
+    if bp is not None:
+        dist_vm, mask_vm, R = bp
+        L = _Labels(n, dist_vm.shape[1], int(R), dist_vm.data_ptr(), mask_vm.data_ptr())
+    _check(load().cbfs_pll_build(ctypes.byref(g), ctypes.byref(L) if L is not None else None, _dptr(order),
+                                 order.numel(), ctypes.byref(params), int(label_cap), _dptr(cnt), _dptr(labels),
+                                 _dptr(ws), ws_bytes, _stream_ptr(stream)), "cbfs_pll_build")
+    return cnt, labels
+
+
+def pll_query(cnt, labels, s, t, bp=None, out=None, stream=None):
+    """``cbfs_pll_query`` for device int32 tensors s, t; int32 answers (uint32 bits)."""
+    torch = _torch()
+    n, cap = labels.shape
+    q = s.numel()
+    ans = out if out is not None else torch.empty(q, dtype=torch.int32, device=s.device)
+    L = None
+    if bp is not None:
+        dist_vm, mask_vm, R = bp
+        L = _Labels(n, dist_vm.shape[1], int(R), dist_vm.data_ptr(), mask_vm.data_ptr())
+    _check(load().cbfs_pll_query(ctypes.byref(L) if L is not None else None, n, cap, _dptr(cnt), _dptr(labels), q,
+                                 _dptr(s), _dptr(t), _dptr(ans), _stream_ptr(stream)), "cbfs_pll_query")
+    return ans
 
 
 def query_local(row_ptr, col, s, t, tau: int, out=None, stream=None):

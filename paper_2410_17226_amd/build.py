@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcbfs.so")
-SOURCES = ["cbfs_run.hip", "cbfs_kernels.hip", "cbfs_query.hip", "cbfs_graph.cpp"]
+SOURCES = ["cbfs_run.hip", "cbfs_kernels.hip", "cbfs_query.hip", "cbfs_pll.hip", "cbfs_graph.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -18,6 +18,7 @@
 
 #include "cbfs.h"
 #include "cbfs_internal.h"
+#include "cbfs_labels.h"
 
 namespace cbfs {
 
@@ -52,22 +53,9 @@ __global__ __launch_bounds__(256) void k_query(int64_t n, int32_t C, int32_t R, 
     const uint64_t *ms_row = mask_vm + s * C * L, *mt_row = mask_vm + t * C * L;
     uint32_t best = CBFS_UNREACHED;
     for (int32_t c = lane; c < C; c += 64) {
-        const uint32_t ds = ds_row[c], dt = dt_row[c];
-        if (ds == CBFS_UNREACHED || dt == CBFS_UNREACHED) continue;
-        const uint64_t *ms = ms_row + (int64_t)c * L;  // ms[a + R] = M_a(s), a in [-R, R-1]
-        const uint64_t *mt = mt_row + (int64_t)c * L;
-        int32_t corr = 0;
-        for (int32_t sum = -2 * R; sum < 0 && corr == 0; sum++) {
-            const int32_t alo = sum - (R - 1) > -R ? sum - (R - 1) : -R;  // b = sum - a <= R - 1
-            const int32_t ahi = sum + R < R - 1 ? sum + R : R - 1;        // b >= -R
-            for (int32_t a = alo; a <= ahi; a++) {
-                if (ms[a + R] & mt[sum - a + R]) {
-                    corr = sum;
-                    break;
-                }
-            }
-        }
-        const uint32_t val = (uint32_t)((int64_t)ds + (int64_t)dt + corr);
+        // ms[a + R] = M_a(s), a in [-R, R-1]
+        const uint32_t val = cluster_pair_value(ds_row[c], dt_row[c], ms_row + (int64_t)c * L,
+                                                mt_row + (int64_t)c * L, R);
         best = val < best ? val : best;
     }
 #pragma unroll
