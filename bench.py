@@ -233,6 +233,84 @@ def local_search_table(P, torch, rp_d, col_d, dvm, mvm, qs_d, qt_d, exact, taus,
     return rows
 
 
+def pll_table(P, torch, dev, scale=16, clusters=16, label_cap=2048, pairs=512, cpu=True):
+    """The exact distance oracle of the paper's appendix on an R-MAT graph:
+    phase 1 = C-BFS labels of `clusters` landmark clusters (Section 4.2's
+    selection, 64 sources, d = 2), phase 2 = pruned BFS from every other vertex
+    in batches of 200 * 1.5^i (at most 1000).  Device times of both phases,
+    label sizes, the device query rate over 10^6 random pairs, and exactness on
+    sampled pairs against a GPU batch of single-source searches; with `cpu`,
+    the oracle's phase 2 on the same input, timed on the host."""
+    import synth
+    n_in, s, d = synth.rmat_edges(scale, 16, seed=77)
+    rp, col, _ = P.build_csr(n_in, s, d)
+    n, m = rp.size - 1, col.size
+    rp_d, col_d = torch.from_numpy(rp).to(dev), torch.from_numpy(col).to(dev)
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    cp, src = P.select_landmarks(rp, col, clusters, 64, 2)
+    ev[0].record(st)
+    dist, masks, stat = P.run_batch(rp_d, col_d, cp, src, 1)
+    dvm, mvm = P.labels_pack(dist, masks, 1)
+    ev[1].record(st)
+    deg = np.diff(rp)
+    order = np.lexsort((np.arange(n), -deg)).astype(np.int32)
+    order = order[~np.isin(order, src)]
+    order_d = torch.from_numpy(order).to(dev)
+    bp = (dvm, mvm, 1)
+    P.pll_build(rp_d, col_d, order_d, bp=bp, label_cap=label_cap)  # warm-up
+    ev[2].record(st)
+    cnt_d, lab_d = P.pll_build(rp_d, col_d, order_d, bp=bp, label_cap=label_cap)
+    ev[3].record(st)
+    torch.cuda.synchronize()
+    assert (stat.cpu().numpy() == 0).all()
+    cnt = cnt_d.cpu().numpy()
+    qn = 1_000_000
+    qs, qt = synth.query_pairs(n, qn, 78)
+    qs_d, qt_d = torch.from_numpy(qs).to(dev), torch.from_numpy(qt).to(dev)
+    ans_d = torch.empty(qn, dtype=torch.int32, device=dev)
+    P.pll_query(cnt_d, lab_d, qs_d, qt_d, bp=bp, out=ans_d)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    P.pll_query(cnt_d, lab_d, qs_d, qt_d, bp=bp, out=ans_d)
+    e1.record(st)
+    torch.cuda.synchronize()
+    q_ms = e0.elapsed_time(e1)
+    # exactness on sampled pairs: exact distances from a batch of single-source searches
+    one = np.arange(pairs + 1, dtype=np.int32)
+    ex_d, _, ex_st = P.run_batch(rp_d, col_d, one, qs[:pairs], 0)
+    exact = ex_d.cpu().numpy().view(np.uint32)[np.arange(pairs), qt[:pairs]]
+    got = ans_d[:pairs].cpu().numpy().view(np.uint32)
+    out = {"graph": f"R-MAT scale {scale} ef 16", "n": int(n), "m_arcs": int(m), "phase1_clusters": int(cp.size - 1),
+           "phase1_sources": int(cp[-1]), "phase2_roots": int(order.size),
+           "batches": len(_pll_batches(order.size)),
+           "phase1_ms": round(ev[0].elapsed_time(ev[1]), 3), "phase2_ms": round(ev[2].elapsed_time(ev[3]), 3),
+           "labels_per_vertex_mean": round(float(cnt.mean()), 2), "labels_per_vertex_max": int(cnt.max()),
+           "index_bytes": int(cnt.sum() * 8 + dvm.numel() * 4 + mvm.numel() * 8),
+           "device_qps_1M": round(qn / (q_ms * 1e-3), 1), "exact_on_sampled_pairs": bool(np.array_equal(got, exact)),
+           "sampled_pairs": pairs}
+    if cpu:
+        import oracle
+        od, om, _ = oracle.cbfs(rp, col, cp, src, R=1)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t = time.time()
+        ocnt, olab = oracle.pll(rp, col, order, bp=(od, om), label_cap=label_cap, nthreads=threads)
+        cpu_s = time.time() - t
+        out["cpu_baseline"] = {"kind": "oracle", "phase2_s": round(cpu_s, 2), "cores": threads,
+                               "same_labels_as_gpu": bool(np.array_equal(ocnt, cnt))}
+    return out
+
+
+def _pll_batches(count, first=200, growth=1.5, max_batch=1000):
+    out, b, lo = [], first, 0
+    while lo < count:
+        size = min(b, count - lo)
+        out.append(size)
+        lo += size
+        b = max(1, min(max_batch, int(b * growth)))
+    return out
+
+
 def rmat14_latency(P, torch, dev):
     """The one-cluster R-MAT scale-14 workload: time of one cbfs_run_batch
     (median of 20 after 3 warm-ups), graph and outputs resident."""
@@ -288,6 +366,9 @@ def main():
                          "exact distances computed on the GPU")
     ap.add_argument("--local-taus", default="128,256,512,1024,2048",
                     help="with --ll: local search sizes (vertices per side) combined with the 128-cluster labels")
+    ap.add_argument("--pll", type=int, default=0, metavar="SCALE",
+                    help="also build the exact 2-hop oracle (pruned landmark labeling) on an R-MAT graph of this scale")
+    ap.add_argument("--pll-cap", type=int, default=2048, help="label capacity per vertex of the exact oracle")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the launch knobs on the first 16 clusters before timing (untimed)")
     ap.add_argument("--copy-only", type=int, default=0,
@@ -534,6 +615,9 @@ def main():
     ll = ll_distortion(P, torch, rp, col, rp_d, col_d, local_taus=taus) if args.ll else None
     if ll:
         print(f"[bench] landmark labeling: {ll}", file=sys.stderr, flush=True)
+    pll = pll_table(P, torch, dev, scale=args.pll, label_cap=args.pll_cap, cpu=not args.no_cpu) if args.pll else None
+    if pll:
+        print(f"[bench] exact oracle: {pll}", file=sys.stderr, flush=True)
     r14 = None
     if not args.no_rmat14 and args.workload == "rmat22":
         r14 = rmat14_latency(P, torch, dev)
@@ -555,6 +639,8 @@ def main():
         line["diameters"] = dtab
     if ll:
         line["landmark_labeling"] = ll
+    if pll:
+        line["exact_oracle"] = pll
     if stats["mode"] == 2 or args.workload == "grid4096":
         line["levels_per_s"] = round(stats["rounds"] / (step_ms * 1e-3), 1)
     print(json.dumps(line), flush=True)
