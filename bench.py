@@ -155,21 +155,25 @@ def diameter_table(P, torch, rp, col, rp_d, col_d, m):
     return rows
 
 
-def ll_distortion(P, torch, rp, col, rp_d, col_d, pairs=512, seed=91, local_taus=()):
+def ll_distortion(P, torch, rp, col, rp_d, col_d, pairs=4096, seed=91, local_taus=(), budget=0):
     """Landmark labeling as Section 4.2 builds it (clusters of 64 selected by
     degree with marking, d = 2, star labels with offsets -1 and 0) for several
     label counts; distortion of the query answer against exact distances from
     a GPU batch of single-source searches (radius 0).  With ``local_taus``,
     the 128-cluster labels are also combined with the bidirectional local
-    search of Appendix B for each tau."""
+    search of Appendix B for each tau; with ``budget``, the memory-budget
+    comparison of plain landmarks and clusters of 8 .. 64 sources."""
     import synth
     n = rp.size - 1
     qs, qt = synth.query_pairs(n, pairs, seed)
-    one = np.arange(pairs + 1, dtype=np.int32)
-    ex_d, _, ex_st = P.run_batch(rp_d, col_d, one, qs, 0)
-    exact = ex_d.cpu().numpy().view(np.uint32)[np.arange(pairs), qt].astype(np.int64)
-    del ex_d
-    assert (ex_st.cpu().numpy() == 0).all()
+    exact = np.empty(pairs, np.int64)
+    for lo in range(0, pairs, 512):  # exact distances, 512 single-source searches at a time
+        hi = min(pairs, lo + 512)
+        one = np.arange(hi - lo + 1, dtype=np.int32)
+        ex_d, ex_m, ex_st = P.run_batch(rp_d, col_d, one, qs[lo:hi], 0)
+        exact[lo:hi] = ex_d.cpu().numpy().view(np.uint32)[np.arange(hi - lo), qt[lo:hi]]
+        assert (ex_st.cpu().numpy() == 0).all()
+        del ex_d, ex_m
     qs_d, qt_d = torch.from_numpy(qs).to(rp_d.device), torch.from_numpy(qt).to(rp_d.device)
     out = []
     for r in (16, 64, 128):
@@ -188,7 +192,64 @@ def ll_distortion(P, torch, rp, col, rp_d, col_d, pairs=512, seed=91, local_taus
             row["local_search"] = local_search_table(P, torch, rp_d, col_d, dvm, mvm, qs_d, qt_d, exact, local_taus)
         out.append(row)
         del dist, masks, dvm, mvm
+    if budget:
+        out.append({"memory_budget_bytes_per_vertex": budget,
+                    "rows": ll_budget_table(P, torch, rp, col, rp_d, col_d, qs_d, qt_d, exact, budget)})
     return out
+
+
+def ll_budget_table(P, torch, rp, col, rp_d, col_d, qs_d, qt_d, exact, budget=1024, timed_queries=1 << 20):
+    """Section 5.3's landmark-labeling comparison under a memory budget of
+    `budget` bytes per vertex: plain landmarks (one distance byte each, the
+    highest-degree vertices) against clusters of w = 8, 16, 32, 64 sources
+    (Section 4.2's selection, d = 2, stored as one distance byte and two w-bit
+    subsets: budget / (1 + w / 4) clusters).  Per configuration: device time of
+    the index (C-BFS batch + compact packing), error of the answers on the
+    sampled pairs, and the device query rate."""
+    import synth
+    n = rp.size - 1
+    st = torch.cuda.current_stream()
+    ts, tt = synth.query_pairs(n, timed_queries, 95)
+    ts_d, tt_d = torch.from_numpy(ts).to(rp_d.device), torch.from_numpy(tt).to(rp_d.device)
+    out_d = torch.empty(timed_queries, dtype=torch.int32, device=rp_d.device)
+    pos = exact > 0
+    rows = []
+    for w in (0, 8, 16, 32, 64):
+        if w == 0:
+            lm = P.top_degree(rp, budget).astype(np.int32)
+            cp, src, R, wq = np.arange(lm.size + 1, dtype=np.int32), lm, 0, 8
+        else:
+            cp, src = P.select_landmarks(rp, col, budget // (1 + w // 4), w, 2)
+            R, wq = 1, w
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        dist, masks, stat = P.run_batch(rp_d, col_d, cp, src, R)
+        d8, mc = P.labels_pack_compact(dist, masks, R, wq)
+        e1.record(st)
+        torch.cuda.synchronize()
+        build_ms = e0.elapsed_time(e1)
+        assert (stat.cpu().numpy() == 0).all()
+        del dist, masks
+        C = cp.size - 1
+        a = P.query_batch_compact(d8, mc, R, wq, qs_d, qt_d).cpu().numpy().view(np.uint32).astype(np.int64)
+        times = []
+        for _ in range(3):
+            q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            q0.record(st)
+            P.query_batch_compact(d8, mc, R, wq, ts_d, tt_d, out=out_d, stream=st)
+            q1.record(st)
+            q1.synchronize()
+            times.append(q0.elapsed_time(q1))
+        rows.append({"w": w if w else "plain", "clusters": int(C), "landmarks": int(cp[-1]),
+                     "bytes_per_vertex": int(C * (1 if w == 0 else 1 + w // 4)),
+                     "index_ms": round(build_ms, 2),
+                     "error_pct": round(float((a[pos] / exact[pos]).mean() - 1.0) * 100, 3),
+                     "exact_fraction": round(float((a[pos] == exact[pos]).mean()), 4),
+                     "bound_holds": bool((a >= exact).all()),
+                     "device_qps": round(timed_queries / (float(np.median(times)) * 1e-3), 1)})
+        print(f"[bench] budget {budget} B/vertex: {rows[-1]}", file=sys.stderr, flush=True)
+        del d8, mc
+    return rows
 
 
 def local_search_table(P, torch, rp_d, col_d, dvm, mvm, qs_d, qt_d, exact, taus, timed_queries=1 << 17):
@@ -364,6 +425,8 @@ def main():
     ap.add_argument("--ll", action="store_true",
                     help="also measure landmark-labeling distortion (clusters selected as in Section 4.2) against "
                          "exact distances computed on the GPU")
+    ap.add_argument("--ll-budget", type=int, default=1024,
+                    help="with --ll: bytes per vertex for the plain / w = 8..64 comparison (0 = skip)")
     ap.add_argument("--local-taus", default="128,256,512,1024,2048",
                     help="with --ll: local search sizes (vertices per side) combined with the 128-cluster labels")
     ap.add_argument("--pll", type=int, default=0, metavar="SCALE",
@@ -612,7 +675,7 @@ def main():
     if dtab:
         print(f"[bench] diameters: {dtab}", file=sys.stderr, flush=True)
     taus = [int(x) for x in args.local_taus.split(",") if x.strip()]
-    ll = ll_distortion(P, torch, rp, col, rp_d, col_d, local_taus=taus) if args.ll else None
+    ll = ll_distortion(P, torch, rp, col, rp_d, col_d, local_taus=taus, budget=args.ll_budget) if args.ll else None
     if ll:
         print(f"[bench] landmark labeling: {ll}", file=sys.stderr, flush=True)
     pll = pll_table(P, torch, dev, scale=args.pll, label_cap=args.pll_cap, cpu=not args.no_cpu) if args.pll else None

@@ -409,6 +409,37 @@ cbfs_status cbfs_query_batch(const cbfs_labels *L, int64_t q, const int32_t *s, 
                              uint32_t *ans, void *stream);
 
 /* ------------------------------------------------------------------------ *
+ * Compact labels under a memory budget (Section 5.3, landmark-labeling
+ * experiments): a cluster of at most w sources stores, per vertex, a one-byte
+ * distance and its 2R subsets as w-bit words, 1 + 2R w / 8 bytes (R = 1:
+ * 3 bytes at w = 8, 17 at w = 64); with a budget of t bytes per vertex, t /
+ * (1 + 2R w / 8) clusters fit.
+ *
+ * cbfs_labels_pack_compact: cluster-major C-BFS outputs (dist [C][n], masks
+ * [C][2R+1][n][1], device) -> dist8 [n][C] (uint8, 255 = unreached) and
+ * masks_out [n][C][2R] w-bit words (offsets -R .. R-1; uint8/16/32/64 for
+ * w = 8/16/32/64; may be NULL for R = 0), device, caller-owned.  Waits for the
+ * stream at its end.  Errors: CBFS_E_ARG; CBFS_E_RANGE (a distance >= 255, or
+ * a source bit at or above w: the outputs are then not usable); CBFS_E_HIP.
+ *
+ * cbfs_query_batch_compact: cbfs_query_batch over compact labels (the same
+ * answers while every distance is below 255).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;              /* vertices                                  */
+    int32_t num_clusters;   /* C                                         */
+    int32_t radius;         /* R                                         */
+    int32_t w;              /* mask width in bits: 8, 16, 32 or 64       */
+    const uint8_t *dist8;   /* device [n][C], 255 = unreached            */
+    const void *masks;      /* device [n][C][2R] w-bit words             */
+} cbfs_compact_labels;
+
+cbfs_status cbfs_labels_pack_compact(const uint32_t *dist, const uint64_t *masks, int32_t num_clusters, int64_t n,
+                                     int32_t radius, int32_t w, uint8_t *dist8, void *masks_out, void *stream);
+cbfs_status cbfs_query_batch_compact(const cbfs_compact_labels *L, int64_t q, const int32_t *s, const int32_t *t,
+                                     uint32_t *ans, void *stream);
+
+/* ------------------------------------------------------------------------ *
  * Bidirectional local search of the query path (Appendix B, "Applying
  * Bi-Directional Search in the Queries").  From each endpoint a BFS in FIFO
  * order (root first, then each dequeued vertex's neighbours in the order of

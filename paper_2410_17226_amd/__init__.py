@@ -13,7 +13,7 @@ from ._binding import (  # noqa: F401
     planes_of,
     build_csr, top_degree, select_clusters, select_landmarks,
     Tuning, run_batch_workspace_size, run_batch, autotune, run_batch_static, STATIC_SCRATCH_BYTES,
-    labels_pack, query_batch, query_local, LOCAL_TAU_MAX, pll_build, pll_query, PLL_LABEL_CAP_MAX,
+    labels_pack, query_batch, labels_pack_compact, query_batch_compact, query_local, LOCAL_TAU_MAX, pll_build, pll_query, PLL_LABEL_CAP_MAX,
     status_string,
     last_run_stats, profile_enable, profile_read, KERNEL_KINDS, release,
 )

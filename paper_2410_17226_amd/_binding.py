@@ -26,7 +26,8 @@ SYMBOLS = [
     "cbfs_last_run_stats", "cbfs_profile_enable", "cbfs_profile_read",
     "cbfs_labels_pack", "cbfs_query_batch", "cbfs_autotune_workspace_size", "cbfs_autotune",
     "cbfs_release", "cbfs_run_batch_static", "cbfs_select_landmarks", "cbfs_query_local",
-    "cbfs_pll_workspace_size", "cbfs_pll_build", "cbfs_pll_query",
+    "cbfs_pll_workspace_size", "cbfs_pll_build", "cbfs_pll_query", "cbfs_labels_pack_compact",
+    "cbfs_query_batch_compact",
 ]
 KERNEL_KINDS = ["tiles", "init", "seed", "push", "pull", "finalize", "persistent", "labels", "query", "local", "pll"]
 
@@ -65,6 +66,11 @@ class _RunStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "groups", "group_words", "slots", "mode", "rounds", "push_rounds", "pull_rounds",
         "frontier_vertices", "frontier_arcs", "device_error", "persistent_blocks", "pull_frontier_vertices")]
+
+
+class _CompactLabels(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("num_clusters", ctypes.c_int32), ("radius", ctypes.c_int32),
+                ("w", ctypes.c_int32), ("dist8", ctypes.c_void_p), ("masks", ctypes.c_void_p)]
 
 
 class _Labels(ctypes.Structure):
@@ -137,6 +143,10 @@ def load():
     lib.cbfs_labels_pack.restype = i32
     lib.cbfs_query_batch.argtypes = [P, i64, P, P, P, P]
     lib.cbfs_query_batch.restype = i32
+    lib.cbfs_labels_pack_compact.argtypes = [P, P, i32, i64, i32, i32, P, P, P]
+    lib.cbfs_labels_pack_compact.restype = i32
+    lib.cbfs_query_batch_compact.argtypes = [P, i64, P, P, P, P]
+    lib.cbfs_query_batch_compact.restype = i32
     lib.cbfs_pll_workspace_size.argtypes = [i64, P]
     lib.cbfs_pll_workspace_size.restype = sz
     lib.cbfs_pll_build.argtypes = [P, P, P, i64, P, i32, P, P, P, sz, P]
@@ -398,6 +408,34 @@ def labels_pack(dist, masks, R: int, stream=None):
 
 
 LOCAL_TAU_MAX = 2048
+_MASK_DTYPES = {8: "uint8", 16: "int16", 32: "int32", 64: "int64"}
+
+
+def labels_pack_compact(dist, masks, R: int, w: int, stream=None):
+    """``cbfs_labels_pack_compact``: (dist8 uint8[n][C], masks [n][C][2R] of w-bit words) on the device."""
+    torch = _torch()
+    C, Pl, n, W = masks.shape
+    if W != 1:
+        raise ValueError("labels need one mask word per cluster")
+    if w not in _MASK_DTYPES:
+        raise ValueError("w must be 8, 16, 32 or 64")
+    dist8 = torch.empty((n, C), dtype=torch.uint8, device=masks.device)
+    mc = torch.empty((n, C, max(1, 2 * R)), dtype=getattr(torch, _MASK_DTYPES[w]), device=masks.device)
+    _check(load().cbfs_labels_pack_compact(_dptr(dist), _dptr(masks), C, n, int(R), int(w), _dptr(dist8), _dptr(mc),
+                                           _stream_ptr(stream)), "cbfs_labels_pack_compact")
+    return dist8, mc
+
+
+def query_batch_compact(dist8, masks_c, R: int, w: int, s, t, out=None, stream=None):
+    """``cbfs_query_batch_compact`` for device int32 tensors s, t; int32 answers (uint32 bits)."""
+    torch = _torch()
+    n, C = dist8.shape
+    q = s.numel()
+    ans = out if out is not None else torch.empty(q, dtype=torch.int32, device=s.device)
+    L = _CompactLabels(n, C, int(R), int(w), dist8.data_ptr(), masks_c.data_ptr())
+    _check(load().cbfs_query_batch_compact(ctypes.byref(L), q, _dptr(s), _dptr(t), _dptr(ans), _stream_ptr(stream)),
+           "cbfs_query_batch_compact")
+    return ans
 PLL_LABEL_CAP_MAX = 4096
 
 

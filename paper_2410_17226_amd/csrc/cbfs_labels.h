@@ -15,8 +15,9 @@ namespace cbfs {
 // o_x(v), so the minimum over x of d(x, s) + d(x, t) is ds + dt plus the lowest
 // offset sum a + b < 0 whose subsets intersect, else plus 0 (the center).
 // CBFS_UNREACHED when either end is unreached.
-__device__ __forceinline__ uint32_t cluster_pair_value(uint32_t ds, uint32_t dt, const uint64_t *ms,
-                                                       const uint64_t *mt, int32_t R)
+// Masks of any width (w-bit subsets of a cluster of w sources).
+template <typename M>
+__device__ __forceinline__ uint32_t cluster_pair_value(uint32_t ds, uint32_t dt, const M *ms, const M *mt, int32_t R)
 {
     if (ds == CBFS_UNREACHED || dt == CBFS_UNREACHED) return CBFS_UNREACHED;
     int32_t corr = 0;

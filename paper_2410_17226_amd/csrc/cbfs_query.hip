@@ -68,6 +68,60 @@ __global__ __launch_bounds__(256) void k_query(int64_t n, int32_t C, int32_t R, 
 
 
 // ---------------------------------------------------------------------------
+// Compact labels: the storage the paper gives a cluster distance vector under a
+// memory budget (Section 5.3, landmark labeling experiments): a one-byte
+// distance and the 2R subsets as w-bit words, w in {8, 16, 32, 64} the
+// cluster's source count bound; 1 + 2R w / 8 bytes per cluster and vertex.
+// Distance 255 means unreached.
+__device__ int g_pack_err;  // set by a pack that met a distance >= 255 or a source bit >= w
+
+template <typename M>
+__global__ void k_labels_pack_compact(const uint32_t *dist, const uint64_t *masks, int32_t C, int64_t n, int32_t R,
+                                      uint8_t *dist8, M *mask_c)
+{
+    constexpr int WBITS = 8 * sizeof(M);
+    const int64_t P = 2 * (int64_t)R + 1;
+    const int64_t L = 2 * (int64_t)R;
+    const int64_t total = (int64_t)C * n;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = k / n, v = k - c * n;
+        const uint32_t d = dist[k];
+        if (d != CBFS_UNREACHED && d >= 255) atomicExch(&g_pack_err, 1);
+        dist8[v * C + c] = d == CBFS_UNREACHED || d >= 255 ? (uint8_t)255 : (uint8_t)d;
+        M *dst = mask_c + (v * C + c) * L;
+        for (int64_t p = 0; p < L; p++) {
+            const uint64_t m = masks[(c * P + p) * n + v];
+            if (WBITS < 64 && (m >> (WBITS % 64)) != 0) atomicExch(&g_pack_err, 1);
+            dst[p] = (M)m;
+        }
+    }
+}
+
+template <typename M>
+__global__ __launch_bounds__(256) void k_query_compact(int32_t C, int32_t R, const uint8_t *dist8, const M *mask_c,
+                                                       int64_t q, const int32_t *qs, const int32_t *qt, uint32_t *ans)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wave >= q) return;  // wave-uniform
+    const int64_t L = 2 * (int64_t)R;
+    const int64_t s = qs[wave], t = qt[wave];
+    uint32_t best = CBFS_UNREACHED;
+    for (int32_t c = lane; c < C; c += 64) {
+        const uint8_t ds = dist8[s * C + c], dt = dist8[t * C + c];
+        const uint32_t val = cluster_pair_value<M>(ds == 255 ? CBFS_UNREACHED : ds, dt == 255 ? CBFS_UNREACHED : dt,
+                                                   mask_c + (s * C + c) * L, mask_c + (t * C + c) * L, R);
+        best = val < best ? val : best;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = __shfl_xor(best, d, 64);
+        best = o < best ? o : best;
+    }
+    if (lane == 0) ans[wave] = best;
+}
+
+// ---------------------------------------------------------------------------
 // Bidirectional local search of the query path (Appendix B, "Applying
 // Bi-Directional Search in the Queries"): from each endpoint, the first tau
 // vertices a FIFO BFS discovers (root first, then the neighbours of each
@@ -342,4 +396,70 @@ extern "C" cbfs_status cbfs_query_local(const cbfs_csr *g, int64_t q, const int3
     hipError_t e = hipGetLastError();
     prof_end(tok);
     return e == hipSuccess ? CBFS_OK : hip_fail("query_local", e);
+}
+
+extern "C" cbfs_status cbfs_labels_pack_compact(const uint32_t *dist, const uint64_t *masks, int32_t num_clusters,
+                                                int64_t n, int32_t radius, int32_t w, uint8_t *dist8, void *masks_out,
+                                                void *stream)
+{
+    if (!dist || (radius > 0 && (!masks || !masks_out)) || !dist8 || num_clusters < 1 || n < 1 || radius < 0 ||
+        radius > 1024 || (w != 8 && w != 16 && w != 32 && w != 64))
+        return fail(CBFS_E_ARG, "cbfs_labels_pack_compact: bad argument");
+    const hipStream_t st = (hipStream_t)stream;
+    const int zero = 0;
+    hipError_t e;
+    if ((e = hipMemcpyToSymbolAsync(HIP_SYMBOL(g_pack_err), &zero, sizeof(int), 0, hipMemcpyHostToDevice, st)) !=
+        hipSuccess)
+        return hip_fail("compact pack flag", e);
+    const int64_t total = (int64_t)num_clusters * n;
+    const int blocks = (int)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
+    void *tok;
+    prof_begin(CBFS_KERNEL_LABELS, st, &tok);
+    switch (w) {
+    case 8: k_labels_pack_compact<uint8_t><<<blocks, 256, 0, st>>>(dist, masks, num_clusters, n, radius, dist8,
+                                                                    (uint8_t *)masks_out); break;
+    case 16: k_labels_pack_compact<uint16_t><<<blocks, 256, 0, st>>>(dist, masks, num_clusters, n, radius, dist8,
+                                                                      (uint16_t *)masks_out); break;
+    case 32: k_labels_pack_compact<uint32_t><<<blocks, 256, 0, st>>>(dist, masks, num_clusters, n, radius, dist8,
+                                                                      (uint32_t *)masks_out); break;
+    default: k_labels_pack_compact<uint64_t><<<blocks, 256, 0, st>>>(dist, masks, num_clusters, n, radius, dist8,
+                                                                      (uint64_t *)masks_out); break;
+    }
+    e = hipGetLastError();
+    prof_end(tok);
+    if (e != hipSuccess) return hip_fail("labels_pack_compact", e);
+    int err = 0;
+    if ((e = hipMemcpyFromSymbolAsync(&err, HIP_SYMBOL(g_pack_err), sizeof(int), 0, hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail("compact pack flag", e);
+    if (err) return fail(CBFS_E_RANGE, "cbfs_labels_pack_compact: a distance >= 255 or a source beyond w");
+    return CBFS_OK;
+}
+
+extern "C" cbfs_status cbfs_query_batch_compact(const cbfs_compact_labels *L, int64_t q, const int32_t *s,
+                                                const int32_t *t, uint32_t *ans, void *stream)
+{
+    if (!L || !L->dist8 || (L->radius > 0 && !L->masks) || L->n < 1 || L->num_clusters < 1 || L->radius < 0 ||
+        L->radius > 1024 || (L->w != 8 && L->w != 16 && L->w != 32 && L->w != 64) || q < 0 ||
+        (q > 0 && (!s || !t || !ans)))
+        return fail(CBFS_E_ARG, "cbfs_query_batch_compact: bad argument");
+    if (q == 0) return CBFS_OK;
+    const int64_t blocks = (q * 64 + 255) / 256;
+    const hipStream_t st = (hipStream_t)stream;
+    void *tok;
+    prof_begin(CBFS_KERNEL_QUERY, st, &tok);
+    switch (L->w) {
+    case 8: k_query_compact<uint8_t><<<(unsigned)blocks, 256, 0, st>>>(L->num_clusters, L->radius, L->dist8,
+                                                                        (const uint8_t *)L->masks, q, s, t, ans); break;
+    case 16: k_query_compact<uint16_t><<<(unsigned)blocks, 256, 0, st>>>(L->num_clusters, L->radius, L->dist8,
+                                                                          (const uint16_t *)L->masks, q, s, t, ans); break;
+    case 32: k_query_compact<uint32_t><<<(unsigned)blocks, 256, 0, st>>>(L->num_clusters, L->radius, L->dist8,
+                                                                          (const uint32_t *)L->masks, q, s, t, ans); break;
+    default: k_query_compact<uint64_t><<<(unsigned)blocks, 256, 0, st>>>(L->num_clusters, L->radius, L->dist8,
+                                                                          (const uint64_t *)L->masks, q, s, t, ans); break;
+    }
+    hipError_t e = hipGetLastError();
+    prof_end(tok);
+    return e == hipSuccess ? CBFS_OK : hip_fail("query_compact", e);
 }

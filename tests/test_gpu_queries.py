@@ -203,3 +203,69 @@ def test_local_search_rejects_bad_tau():
         with pytest.raises(P.CbfsError):
             P.query_local(rp, col, s, s, tau)
     assert P.query_local(rp, col, s[:0], s[:0], 8).numel() == 0
+
+
+@pytest.mark.parametrize("w", [8, 16, 32, 64])
+def test_compact_labels_under_a_budget(w):
+    """Compact labels (one-byte distance, w-bit subsets; Section 5.3's storage
+    under a memory budget): the packed bytes equal the oracle's outputs packed
+    the same way, and queries over them equal the brute force over the
+    landmarks."""
+    torch = _torch()
+    import paper_2410_17226_amd as P
+    n, s, d = synth.random_graph(500, 0.012, 60 + w)
+    rp, col, _ = P.build_csr(n, s, d)
+    nv = rp.size - 1
+    cp, src = P.select_landmarks(rp, col, 12, w, 2)
+    assert np.diff(cp).max() <= w
+    rp_d, col_d = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    dist, masks, st = P.run_batch(rp_d, col_d, cp, src, 1)
+    assert (st.cpu().numpy() == 0).all()
+    d8, mc = P.labels_pack_compact(dist, masks, 1, w)
+    od, om, _ = oracle.cbfs(rp, col, cp, src, R=1)
+    C = cp.size - 1
+    want_d8 = np.where(od == 0xFFFFFFFF, 255, od).astype(np.uint8).T                  # [n][C]
+    want_m = np.transpose(om[:, :2, :, 0], (2, 0, 1)).astype(np.uint64)              # [n][C][2]: planes -1, 0
+    assert np.array_equal(d8.cpu().numpy(), want_d8)
+    got_m = mc.cpu().numpy().view({8: np.uint8, 16: np.uint16, 32: np.uint32, 64: np.uint64}[w]).astype(np.uint64)
+    assert np.array_equal(got_m, want_m)
+    assert d8.numel() + mc.numel() * mc.element_size() == nv * C * (1 + 2 * w // 8)  # bytes per vertex as budgeted
+    qs, qt = synth.query_pairs(nv, 5000, 70 + w)
+    qs[:30] = src[:30]
+    ans = P.query_batch_compact(d8, mc, 1, w, torch.from_numpy(qs).cuda(), torch.from_numpy(qt).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(ans.cpu().numpy().view(np.uint32), oracle.query_landmarks(rp, col, cp, src, qs, qt))
+
+
+def test_compact_labels_plain_landmarks_and_errors():
+    """Single-vertex landmarks (R = 0, a distance byte only) and the range
+    errors: a cluster wider than w, and a distance of 255 or more."""
+    torch = _torch()
+    import paper_2410_17226_amd as P
+    n, s, d = synth.random_graph(500, 0.012, 81)
+    rp, col, _ = P.build_csr(n, s, d)
+    nv = rp.size - 1
+    lm = P.top_degree(rp, 40).astype(np.int32)
+    cp = np.arange(lm.size + 1, dtype=np.int32)
+    rp_d, col_d = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    dist, masks, st = P.run_batch(rp_d, col_d, cp, lm, 0)
+    d8, mc = P.labels_pack_compact(dist, masks, 0, 8)
+    qs, qt = synth.query_pairs(nv, 3000, 82)
+    ans = P.query_batch_compact(d8, mc, 0, 8, torch.from_numpy(qs).cuda(), torch.from_numpy(qt).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(ans.cpu().numpy().view(np.uint32), oracle.query_landmarks(rp, col, cp, lm, qs, qt))
+    # a cluster of 20 sources does not fit 8-bit subsets
+    cp2, src2 = P.select_landmarks(rp, col, 3, 20, 2)
+    assert np.diff(cp2).max() > 8
+    dist2, masks2, _ = P.run_batch(rp_d, col_d, cp2, src2, 1)
+    with pytest.raises(P.CbfsError) as ei:
+        P.labels_pack_compact(dist2, masks2, 1, 8)
+    assert ei.value.status == -2
+    # a path of 400 vertices: distances beyond one byte
+    e = np.array([(i, i + 1) for i in range(399)], np.int64)
+    prp, pcol, _ = P.build_csr(400, e[:, 0], e[:, 1])
+    pd, pm, _ = P.run_batch(torch.from_numpy(prp).cuda(), torch.from_numpy(pcol).cuda(),
+                            np.array([0, 1], np.int32), np.array([0], np.int32), 0)
+    with pytest.raises(P.CbfsError) as ei:
+        P.labels_pack_compact(pd, pm, 0, 8)
+    assert ei.value.status == -2
