@@ -224,6 +224,12 @@ typedef struct {
                                   256 vertices and at least hub_arcs arcs runs with
                                   blocks that own target ranges (sets merged in LDS, one
                                   store per target); 0 = auto (65536), < 0 = never      */
+    int32_t field_bits;        /* bits a cluster of at most 32 sources takes in a search
+                                  word: 8, 16 or 32 (several clusters share each word),
+                                  or 64 (one cluster per word); 0 = auto (the smallest of
+                                  8, 16, 32 that holds the largest cluster, 64 for
+                                  clusters of more than 32 sources).  Outputs do not
+                                  depend on it.                                          */
 } cbfs_tuning;
 
 /* Bytes of device workspace cbfs_run_batch needs for these arguments. */

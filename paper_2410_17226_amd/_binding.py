@@ -55,7 +55,8 @@ class _Tuning(ctypes.Structure):
                 ("concurrent_groups", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("alpha", ctypes.c_float), ("beta", ctypes.c_float),
                 ("force_pull", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("gamma", ctypes.c_float), ("hub_arcs", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("gamma", ctypes.c_float), ("hub_arcs", ctypes.c_int32),
+                ("field_bits", ctypes.c_int32)]
 
 
 class _Trial(ctypes.Structure):
@@ -92,16 +93,17 @@ class Tuning:
     schedule: int = 0
     gamma: float = 0.0
     hub_arcs: int = 0
+    field_bits: int = 0
 
     @classmethod
     def _from_c(cls, t: _Tuning) -> "Tuning":
         return cls(t.mode, t.group_words, t.concurrent_groups, t.block_size, t.alpha, t.beta, t.force_pull,
-                   t.blocks_per_cu, t.schedule, t.gamma, t.hub_arcs)
+                   t.blocks_per_cu, t.schedule, t.gamma, t.hub_arcs, t.field_bits)
 
     def _c(self) -> _Tuning:
         return _Tuning(self.mode, self.group_words, self.concurrent_groups, self.block_size,
                        self.alpha, self.beta, self.force_pull, self.blocks_per_cu, self.schedule, self.gamma,
-                       self.hub_arcs)
+                       self.hub_arcs, self.field_bits)
 
 
 def load():

@@ -1,7 +1,10 @@
 // Device-side building blocks of the Cluster-BFS level loop (gfx950, wave64).
 //
 // State of one cluster group (several clusters packed into W 64-bit words per
-// vertex; cluster j of the group owns words [j*WC, (j+1)*WC)):
+// vertex; cluster j of the group owns words [j*WC, (j+1)*WC), or, for
+// clusters of at most 32 sources, a field of 2^flog bits: clusters
+// j*F .. j*F + F-1 share word j, F = 64 >> flog, cluster j*F + f at bits
+// [f << flog, (f + 1) << flog) with its center at the field's bit 0):
 //   A, B   [n][W]  the paper's S_next / "seen so far" arrays, double-buffered:
 //                  in round i, cur = (i even ? A : B) holds Seen_i(v), the set
 //                  of sources within distance i of v, complete for every v, and
@@ -75,8 +78,24 @@ struct SlotArgs {
 struct GroupDesc {
     int32_t c0;               // global index of the group's first cluster
     int32_t nc;               // clusters in the group
+    int32_t flog;             // log2 of a cluster's field width: 6 = whole words, 3..5 = 8..32 bits
+    int32_t pad;
     uint64_t full[MAX_W];     // per word: bits of sources present
 };
+
+// Units of a group: WC words each; a unit of one word holds fields_per_word
+// clusters (1 unless fields are narrower than a word).
+__device__ __forceinline__ int32_t fields_per_word(const GroupDesc &g) { return 1 << (6 - g.flog); }
+__device__ __forceinline__ uint64_t field_mask(const GroupDesc &g)
+{
+    return g.flog >= 6 ? ~0ull : ((1ull << (1 << g.flog)) - 1ull);
+}
+template <int WC>
+__device__ __forceinline__ int32_t units_of(const GroupDesc &g)
+{
+    if constexpr (WC > 1) return g.nc;
+    else return (g.nc + fields_per_word(g) - 1) >> (6 - g.flog);
+}
 
 struct OutArgs {
     uint32_t *dist;           // [C][n]
@@ -279,6 +298,10 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
 // without it the caller stores nxt(u) itself (it owns u's row in this round).
 // With active false the words are still read (so a caller can request them
 // before it knows u is in F_i) and nothing is written.
+//
+// j is a unit of the group (units_of): a cluster of WC words, or one word
+// holding several clusters in fields; the unit's thread owns its words, so the
+// seen update stays one plain store.
 template <int W, int WC, bool NXT_OR>
 __device__ __forceinline__ void vertex_phase_cluster(const SlotArgs &s, const GroupDesc &g, const OutArgs &o,
                                                      int64_t n, int32_t round, int32_t u, int32_t j,
@@ -286,9 +309,10 @@ __device__ __forceinline__ void vertex_phase_cluster(const SlotArgs &s, const Gr
 {
     const uint64_t *cp = cur_buf(s, round) + (size_t)u * W + j * WC;
     uint64_t *sp = s.seen + (size_t)u * W + j * WC;
-    // the cluster's distance word is requested with the state words, so the
-    // encode does not wait for a second round trip
-    const uint32_t dold = o.dist[(size_t)(g.c0 + j) * (size_t)n + (size_t)u];
+    const bool fields = WC == 1 && g.flog < 6;
+    // a whole-word cluster's distance word is requested with the state words,
+    // so the encode does not wait for a second round trip
+    const uint32_t dold = fields ? 0u : o.dist[(size_t)(g.c0 + j) * (size_t)n + (size_t)u];
     uint64_t cu[WC], sv[WC], nw[WC];
     uint64_t any = 0;
     const uint64_t am = active ? ~0ull : 0ull;  // a value mask, so the loads stay ahead of the test
@@ -312,7 +336,21 @@ __device__ __forceinline__ void vertex_phase_cluster(const SlotArgs &s, const Gr
         if constexpr (NXT_OR)
             if (nw[x]) or64(nxt_buf(s, round) + (size_t)u * W + j * WC + x, nw[x]);
     }
-    emit_cluster<WC>(o, n, g.c0 + j, u, round, sv, nw, g.full + j * WC, dold);
+    if (!fields) {
+        emit_cluster<WC>(o, n, g.c0 + j, u, round, sv, nw, g.full + j * WC, dold);
+        return;
+    }
+    const int32_t F = fields_per_word(g);
+    const uint64_t fm = field_mask(g);
+    for (int32_t f = 0; f < F; f++) {
+        const int32_t c = g.c0 + j * F + f;
+        if (c >= g.c0 + g.nc) break;
+        const int sh = f << g.flog;
+        const uint64_t nf = (nw[0] >> sh) & fm;
+        if (!nf) continue;
+        const uint64_t pf = (sv[0] >> sh) & fm, ff = (g.full[j] >> sh) & fm;
+        emit_cluster<1>(o, n, c, u, round, &pf, &nf, &ff, o.dist[(size_t)c * (size_t)n + (size_t)u]);
+    }
 }
 
 // The vertex phase of u for every cluster of the group, one after another.
@@ -320,9 +358,10 @@ template <int W, int WC, bool NXT_OR = true>
 __device__ __forceinline__ void vertex_phase(const SlotArgs &s, const GroupDesc &g, const OutArgs &o,
                                              int64_t n, int32_t round, int32_t u)
 {
+    const int32_t units = units_of<WC>(g);
 #pragma unroll 1
     for (int j = 0; j < W / WC; j++) {
-        if (j >= g.nc) break;
+        if (j >= units) break;
         vertex_phase_cluster<W, WC, NXT_OR>(s, g, o, n, round, u, j);
     }
 }

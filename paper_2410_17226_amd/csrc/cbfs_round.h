@@ -125,7 +125,12 @@ __device__ void seed_block(Stager<STAGE_CAP> &st, const SlotArgs &s, const Graph
         while (cluster_ptr[g.c0 + j + 1] <= idx) j++;
         const int32_t i = idx - cluster_ptr[g.c0 + j];
         const int32_t v = sources[idx];
-        or64(s.A + (size_t)v * W + j * WC + (i >> 6), 1ull << (i & 63));
+        if (WC == 1 && g.flog < 6) {  // cluster j in field j % F of word j / F
+            const int32_t F = fields_per_word(g);
+            or64(s.A + (size_t)v * W + j / F, 1ull << (((j % F) << g.flog) + i));
+        } else {
+            or64(s.A + (size_t)v * W + j * WC + (i >> 6), 1ull << (i & 63));
+        }
         claim(st, s.bits0, v, gr.row_ptr[v + 1] - gr.row_ptr[v]);
     }
     stager_flush(st, gr.row_ptr, s.q0, s.ctr + 0);
@@ -828,9 +833,10 @@ __device__ void pull_walk(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     // frontier word (membership only gates the writes); a local row of F_i
     // the arc phase did not store gets nxt(v) = Seen_i(v)
     constexpr int CPV = W / WC;
+    const int32_t units = units_of<WC>(g);
     for (int32_t idx = threadIdx.x; idx < (r1 - r0) * CPV; idx += BLOCK) {
         const int32_t v = r0 + idx / CPV, j = idx % CPV;
-        if (j >= g.nc) continue;
+        if (j >= units) continue;
         const bool in_f = (bits_cur[v >> 6] >> (v & 63)) & 1ull;
         const int32_t k = v - r0;
         if (v < T.loc_lo) {
@@ -1077,9 +1083,10 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
     // (row, cluster); a local row the arc phase did not store gets nxt(v) =
     // Seen_i(v) here, each thread its cluster's words
     constexpr int CPV = W / WC;
+    const int32_t units = units_of<WC>(g);
     for (int32_t idx = threadIdx.x; idx < (r1 - r0) * CPV; idx += BLOCK) {
         const int32_t v = r0 + idx / CPV, j = idx % CPV;
-        if (j >= g.nc || !((bits_cur[v >> 6] >> (v & 63)) & 1ull)) continue;
+        if (j >= units || !((bits_cur[v >> 6] >> (v & 63)) & 1ull)) continue;
         const int32_t k = v - r0;
         if (v < T.loc_lo) {
             vertex_phase_cluster<W, WC, true>(s, g, o, gr.n, round, v, j);  // tile-crossing row
@@ -1204,32 +1211,43 @@ __device__ __forceinline__ void finalize_part(const SlotArgs &s, int64_t n, cons
                                               int64_t tid, int64_t stride)
 {
     const int64_t P = planes_of(o);
+    const bool fields = WC == 1 && g.flog < 6;
+    const int32_t F = fields ? fields_per_word(g) : 1;
+    const uint64_t fm = fields ? field_mask(g) : ~0ull;
     for (int64_t v = tid; v < n; v += stride) {
         uint64_t sv[W];
         load_words<W>(s.seen + (size_t)v * W, sv);
 #pragma unroll
         for (int j = 0; j < W / WC; j++) {
-            if (j >= g.nc) break;
-            const int32_t c = g.c0 + j;
-            const uint64_t *sc = sv + j * WC;
-            bool any = false, full = true;
+            for (int32_t f = 0; f < F; f++) {
+                const int32_t cj = j * F + f;  // cluster index in the group
+                if (cj >= g.nc) break;
+                const int32_t c = g.c0 + cj;
+                uint64_t sc[WC], fl[WC];
 #pragma unroll
-            for (int x = 0; x < WC; x++) {
-                any |= sc[x] != 0;
-                full &= sc[x] == g.full[j * WC + x];
-            }
-            // unreached: by the center (center-relative), or by every source
-            // (min-relative, where Delta_v needs only one)
-            if (o.minrel ? !any : !(sc[0] & 1ull)) {
-                if (any) atomicExch(o.status + c, E_RADIUS);
-                o.dist[(size_t)c * n + v] = UNREACHED;
-                for (int64_t p = 0; p < P; p++) {
-                    uint64_t *dst = o.masks + (((size_t)c * P + p) * (size_t)n + (size_t)v) * WC;
-#pragma unroll
-                    for (int x = 0; x < WC; x++) dst[x] = 0;
+                for (int x = 0; x < WC; x++) {
+                    sc[x] = fields ? (sv[j] >> (f << g.flog)) & fm : sv[j * WC + x];
+                    fl[x] = fields ? (g.full[j] >> (f << g.flog)) & fm : g.full[j * WC + x];
                 }
-            } else if (!full) {
-                atomicExch(o.status + c, E_RADIUS);
+                bool any = false, full = true;
+#pragma unroll
+                for (int x = 0; x < WC; x++) {
+                    any |= sc[x] != 0;
+                    full &= sc[x] == fl[x];
+                }
+                // unreached: by the center (center-relative), or by every source
+                // (min-relative, where Delta_v needs only one)
+                if (o.minrel ? !any : !(sc[0] & 1ull)) {
+                    if (any) atomicExch(o.status + c, E_RADIUS);
+                    o.dist[(size_t)c * n + v] = UNREACHED;
+                    for (int64_t p = 0; p < P; p++) {
+                        uint64_t *dst = o.masks + (((size_t)c * P + p) * (size_t)n + (size_t)v) * WC;
+#pragma unroll
+                        for (int x = 0; x < WC; x++) dst[x] = 0;
+                    }
+                } else if (!full) {
+                    atomicExch(o.status + c, E_RADIUS);
+                }
             }
         }
     }

@@ -100,6 +100,8 @@ struct Plan {
     int32_t minrel = 0;   // CBFS_ENCODE_MIN: R is the cluster diameter, R + 1 planes
     int32_t WC = 1;       // words per cluster (output W)
     int32_t W = 1;        // words per vertex in a group
+    int32_t flog = 6;     // a cluster's field in a search word: 2^flog bits (6 = the whole word)
+    int32_t fpw = 1;      // clusters per word (64 >> flog; WC = 1 when above 1)
     int32_t per_group = 1;
     int32_t groups = 0;
     int32_t slots = 1;
@@ -193,11 +195,22 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
     }
     if (!valid_w(p.W, p.WC))
         return fail(CBFS_E_ARG, "cbfs_tuning: group_words must be one of 1,2,4,8,16 and a multiple of the cluster words");
+    // clusters of at most 32 sources share search words: fields of 8, 16 or
+    // 32 bits (the smallest that holds the largest cluster)
+    {
+        int32_t fb = (t && t->field_bits) ? t->field_bits : (p.WC == 1 && kmax <= 32 ? 8 : 64);
+        if (!(t && t->field_bits))
+            while (fb < 64 && fb < kmax) fb *= 2;
+        if ((fb != 8 && fb != 16 && fb != 32 && fb != 64) || (fb < 64 && fb < kmax))
+            return fail(CBFS_E_ARG, "cbfs_tuning: field_bits must be 8, 16, 32 or 64 and hold the largest cluster");
+        p.flog = fb == 8 ? 3 : (fb == 16 ? 4 : (fb == 32 ? 5 : 6));
+        p.fpw = 64 >> p.flog;
+    }
     // never pack more words than clusters need
-    p.per_group = p.W / p.WC;
+    p.per_group = p.W / p.WC * p.fpw;
     while (p.per_group > 1 && p.per_group / 2 >= p.C && valid_w(p.W / 2, p.WC)) {
         p.W /= 2;
-        p.per_group = p.W / p.WC;
+        p.per_group = p.W / p.WC * p.fpw;
     }
     p.groups = (p.C + p.per_group - 1) / p.per_group;
     if (p.mode == CBFS_MODE_PERSISTENT) {
@@ -274,8 +287,13 @@ static GroupDesc group_desc(const Plan &p, const cbfs_batch *b, int32_t grp)
     GroupDesc d{};
     d.c0 = grp * p.per_group;
     d.nc = std::min(p.per_group, p.C - d.c0);
+    d.flog = p.flog;
     for (int j = 0; j < d.nc; j++) {
         const int32_t k = b->cluster_ptr[d.c0 + j + 1] - b->cluster_ptr[d.c0 + j];
+        if (p.fpw > 1) {  // cluster j in field j % fpw of word j / fpw
+            d.full[j / p.fpw] |= ((1ull << k) - 1) << ((j % p.fpw) << p.flog);
+            continue;
+        }
         for (int x = 0; x < p.WC; x++) {
             const int lo = 64 * x;
             uint64_t w = 0;

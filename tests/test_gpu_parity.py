@@ -76,20 +76,27 @@ TUNINGS = [None, dict(alpha=-1.0), dict(force_pull=1), dict(group_words=1), dict
            dict(mode=1, hub_arcs=1), dict(mode=1, alpha=-1.0, hub_arcs=1),
            dict(mode=1, alpha=-1.0, hub_arcs=1, group_words=16), dict(mode=1, alpha=-1.0, hub_arcs=1, group_words=1),
            dict(mode=1, hub_arcs=-1), dict(mode=2, group_words=16, concurrent_groups=4),
-           dict(mode=2, group_words=16, force_pull=1, gamma=1e-9, concurrent_groups=3)]
+           dict(mode=2, group_words=16, force_pull=1, gamma=1e-9, concurrent_groups=3),
+           dict(field_bits=64), dict(mode=2, field_bits=64, group_words=1, concurrent_groups=5),
+           dict(field_bits=32, force_pull=1, gamma=1e-9), dict(mode=2, field_bits=8, concurrent_groups=3)]
 TUNING_IDS = ["default", "push", "pull", "w1", "w8", "host", "host_pull_w2", "host_push", "slots3", "slots64",
               "host_pull_all", "pers_pull_all", "always_test", "w16", "w16_pull_all",
               "hub", "hub_push_all", "hub_push_all_w16", "hub_push_all_w1", "no_hub", "pers_w16",
-              "pers_w16_pull_all"]
+              "pers_w16_pull_all", "unpacked", "pers_unpacked", "fields32_pull_all", "pers_fields8"]
 
 
-def tuning_of(t, WC=1):
+def tuning_of(t, WC=1, kmax=64):
     import paper_2410_17226_amd as P
     if t is None:
         return None
     t = dict(t)
     if "group_words" in t and (t["group_words"] % WC or (WC == 3 and t["group_words"] != 3)):
         t["group_words"] = WC
+    if "field_bits" in t:  # the narrowest allowed field that holds the largest cluster
+        fb = t["field_bits"]
+        while fb < 64 and fb < kmax:
+            fb *= 2
+        t["field_bits"] = fb
     return P.Tuning(**t)
 
 
@@ -117,7 +124,7 @@ def test_parity_small(name, gen, R, k, tun):
         if rp.size - 1 >= ncent else np.arange(rp.size - 1, dtype=np.int32), k, hops)
     rp, col, cp, src = ours
     WC = (int(np.diff(cp).max()) + 63) // 64
-    gpu = gpu_cbfs(rp, col, cp, src, R, tuning_of(tun, WC))
+    gpu = gpu_cbfs(rp, col, cp, src, R, tuning_of(tun, WC, int(np.diff(cp).max())))
     ref = oracle.cbfs(*ref_in, R=R)
     assert_same(gpu, ref, name)
 
@@ -181,8 +188,8 @@ def test_parity_radius_zero():
 
 MIN_TUNINGS = [None, dict(alpha=-1.0), dict(force_pull=1), dict(mode=1, force_pull=1, gamma=1e-9),
                dict(mode=1, group_words=16), dict(mode=2, concurrent_groups=4, group_words=1),
-               dict(mode=1, alpha=-1.0, hub_arcs=1)]
-MIN_IDS = ["default", "push", "pull", "pull_wave", "w16", "persistent", "hub_push"]
+               dict(mode=1, alpha=-1.0, hub_arcs=1), dict(field_bits=64)]
+MIN_IDS = ["default", "push", "pull", "pull_wave", "w16", "persistent", "hub_push", "unpacked"]
 
 
 def min_cases():
@@ -298,3 +305,36 @@ def test_autotuned_knobs_keep_every_bit():
         if ms >= 0:
             assert_same(gpu_cbfs(rp, col, cp, src, cfg["R"], t), ref, f"trial {t}")
 
+
+
+PACKED_TUNINGS = [None, dict(force_pull=1, gamma=1e-9), dict(alpha=-1.0), dict(mode=2, concurrent_groups=3),
+                  dict(mode=2, group_words=1, concurrent_groups=7), dict(group_words=2, force_pull=1)]
+
+
+@pytest.mark.parametrize("fb", [8, 16, 32])
+@pytest.mark.parametrize("R", [1, 2])
+@pytest.mark.parametrize("ti", range(len(PACKED_TUNINGS)))
+def test_parity_packed_fields(fb, R, ti):
+    """Clusters of at most 32 sources sharing search words (fields of 8, 16 or
+    32 bits): clusters that fill their field exactly, smaller ones, a count of
+    clusters that leaves the last word partly empty, a cluster whose radius is
+    violated next to valid ones, and a cluster that does not reach every
+    vertex; outputs word for word against the oracle."""
+    torch = _torch()
+    import paper_2410_17226_amd as P
+    n, s, d = synth.random_graph(300, {8: 0.04, 16: 0.06, 32: 0.13}[fb], 90 + fb + R)
+    rp, col, _ = P.build_csr(n, s, d, flags=7)
+    nv = rp.size - 1
+    rng = np.random.default_rng(fb * 10 + R)
+    centers = rng.choice(nv, 13, replace=False).astype(np.int32)
+    cp, src = P.select_clusters(rp, col, centers, fb, R)   # balls capped at fb sources: many fill their field
+    # one more cluster of scattered sources (a radius violation among valid clusters), then a single source
+    extra = rng.choice(np.setdiff1d(np.arange(nv), src), max(2, fb // 2), replace=False).astype(np.int32)
+    cp = np.concatenate([cp, [cp[-1] + extra.size, cp[-1] + extra.size + 1]]).astype(np.int32)
+    src = np.concatenate([src, extra, [centers[0]]]).astype(np.int32)
+    assert np.diff(cp).max() <= fb and (np.diff(cp) == fb).any()
+    tun = PACKED_TUNINGS[ti]
+    t = P.Tuning(**{**(tun or {}), "field_bits": fb})
+    gpu = gpu_cbfs(rp, col, cp, src, R, t)
+    ref = oracle.cbfs(rp, col, cp, src, R=R)
+    assert_same(gpu, ref, f"fields of {fb} bits, R={R}, {tun}")

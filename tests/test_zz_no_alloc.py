@@ -82,7 +82,7 @@ def test_static_refuses_a_batch_beyond_its_scratch():
     import paper_2410_17226_amd as P
     rp, col, cp, src, R = _small_grid(512, 16, 5)
     rp_d, col_d = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
-    t = P.Tuning(mode=P.CBFS_MODE_PERSISTENT)
+    t = P.Tuning(mode=P.CBFS_MODE_PERSISTENT, field_bits=64)  # one cluster per word: 16 group slots
     assert P.run_batch_workspace_size(rp_d, col_d, cp, src, R, t) > P.STATIC_SCRATCH_BYTES
     with pytest.raises(P.CbfsError) as ei:
         P.run_batch_static(rp_d, col_d, cp, src, R, t)
