@@ -237,8 +237,10 @@ size_t cbfs_run_batch_workspace_size(const cbfs_csr *g, const cbfs_batch *b, con
 
 /*
  *   dist           device [C][n]          uint32 output
- *   masks          device [C][P][n][W]    uint64 output, P = 2R+1 (center) or
- *                                         d+1 (min, d = radius)
+ *   masks          device [C][P][n][WC]   uint64 output, WC = ceil(k_max / 64)
+ *                                         words per cluster (k_max: the largest
+ *                                         cluster), P = 2R+1 (center) or d+1
+ *                                         (min, d = radius)
  *   cluster_status device [C]             int32 output
  *   workspace      device, workspace_bytes >= cbfs_run_batch_workspace_size(...)
  * Ordering: everything is enqueued on `stream`.  In CBFS_MODE_PERSISTENT the
