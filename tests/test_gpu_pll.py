@@ -98,3 +98,34 @@ def test_pll_label_capacity_and_arguments():
     for bad in (dict(label_cap=0), dict(label_cap=P.PLL_LABEL_CAP_MAX + 1), dict(growth=0.5)):
         with pytest.raises(P.CbfsError):
             P.pll_build(rp_d, col_d, order_d, **{"label_cap": 64, **bad})
+
+
+def test_pll_rmat14_full_schedule_matches_oracle():
+    """R-MAT 14 (about 12K roots: the paper's batch schedule reaches its cap of
+    1,000 roots and runs 16 batches), phase 1 of 8 landmark clusters: labels
+    equal the oracle's entry for entry, and 20,000 queries are exact."""
+    torch = _torch()
+    import paper_2410_17226_amd as P
+    n, s, d = synth.rmat_edges(14, 16, seed=41)
+    rp, col, rp_d, col_d, nv, _, _, _ = _setup(torch, P, n, s, d, 15, False)
+    cp, src = P.select_landmarks(rp, col, 8, 64, 2)
+    dist, masks, st = P.run_batch(rp_d, col_d, cp, src, 1)
+    dvm, mvm = P.labels_pack(dist, masks, 1)
+    od, om, _ = oracle.cbfs(rp, col, cp, src, R=1)
+    deg = np.diff(rp)
+    order = np.lexsort((np.arange(nv), -deg)).astype(np.int32)
+    order = order[~np.isin(order, src)]
+    assert len(oracle.pll_batches(order.size)) >= 12
+    print(f"[pll] rmat14 n={nv} roots={order.size}", flush=True)
+    cnt_d, lab_d = P.pll_build(rp_d, col_d, torch.from_numpy(order).cuda(), bp=(dvm, mvm, 1), label_cap=1024)
+    torch.cuda.synchronize()
+    cnt = cnt_d.cpu().numpy()
+    lab = lab_d.cpu().numpy().view(np.uint64)
+    ocnt, olab = oracle.pll(rp, col, order, bp=(od, om), label_cap=1024)
+    assert np.array_equal(cnt, ocnt)
+    mask = np.arange(1024)[None, :] < cnt[:, None]
+    assert np.array_equal(lab[mask], olab[mask])
+    qs, qt = synth.query_pairs(nv, 20000, 43)
+    ans = P.pll_query(cnt_d, lab_d, torch.from_numpy(qs).cuda(), torch.from_numpy(qt).cuda(), bp=(dvm, mvm, 1))
+    torch.cuda.synchronize()
+    assert np.array_equal(ans.cpu().numpy().view(np.uint32), oracle.pair_distances(rp, col, qs, qt))
