@@ -25,7 +25,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <vector>
 
 #include "cbfs.h"
 #include "cbfs_internal.h"
