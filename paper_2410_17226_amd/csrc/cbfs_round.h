@@ -48,6 +48,17 @@ struct PullSmem {
     };
 };
 
+// The wave form's arc -> row map: per arc of the tile its row (minus the
+// tile's first row) and three flags.
+constexpr int AROW_ROW = 0x1fff;
+constexpr int AROW_LAST = 0x2000;   // the row's last arc in the tile
+constexpr int AROW_FIRST = 0x4000;  // the row's first arc
+constexpr int AROW_DONE = 0x8000;   // the row's set was complete when the round began
+static_assert(TILE_ITEMS <= AROW_ROW, "a tile's row offsets fit the arc -> row map's row field");
+
+// lanes 0..al of a word of lane bits
+__device__ __forceinline__ uint64_t lane_mask_upto(int al) { return al >= 63 ? ~0ull : (2ull << al) - 1ull; }
+
 template <int W>
 union RoundSmem {
     PushSmem<W> push;
@@ -900,9 +911,16 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
             sm.wv.arow[k] = (uint16_t)m;
         }
         const int before = block_exclusive_max(m, sm.tmp);
-        if (before > 0)
-            for (int32_t k = lo; k < hi; k++)
-                if ((int)sm.wv.arow[k] < before) sm.wv.arow[k] = (uint16_t)before;
+        // the final row of each arc, with the facts a step needs about it
+        for (int32_t k = lo; k < hi; k++) {
+            int r = sm.wv.arow[k];
+            r = r > before ? r : before;
+            int a = r;
+            if (k + 1 == (int32_t)sm.rend[r]) a |= AROW_LAST;
+            if (k == rstart_off(r)) a |= AROW_FIRST;
+            if ((sm.fin[r >> 6] >> (r & 63)) & 1ull) a |= AROW_DONE;
+            sm.wv.arow[k] = (uint16_t)a;
+        }
     }
     __syncthreads();
 
@@ -967,16 +985,17 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
         int32_t next = base + AL;
         const int32_t k = base + al;
         const bool in = k < wb;
-        const int32_t rk = in ? (int32_t)sm.wv.arow[k] : 0;  // a valid row index on every lane
-        const bool active = in && !((sm.fin[rk >> 6] >> (rk & 63)) & 1ull);
-        const int32_t re = in ? (int32_t)sm.rend[rk] : 0;
+        const int32_t a = in ? (int32_t)sm.wv.arow[k] : 0;
+        const int32_t rk = a & AROW_ROW;  // a valid row index on every lane
+        const bool active = in && !(a & AROW_DONE);
+        const bool last = in && (a & AROW_LAST);  // the row's last arc in the tile
         // a row that will carry out of this step and was not carried into it:
         // its words go out with this step's gathers, so the completeness test
         // at the step's end already covers its first AL arcs
         {
             const int32_t rl = __builtin_amdgcn_readlane(rk, AL - 1);
-            const int32_t rel = __builtin_amdgcn_readlane(re, AL - 1);
-            if (base + AL < wb && rel != base + AL && rl != crow)
+            const int32_t ll = __builtin_amdgcn_readlane((int)last, AL - 1);
+            if (base + AL < wb && !ll && rl != crow)
                 load_words<WL>(cur + (size_t)(r0 + rl) * W + hw, ccv);
         }
         uint64_t x[WL];
@@ -986,21 +1005,22 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
             const int32_t u = active ? gr.col[e0 + k] : r0;
             const uint64_t hm = active ? ~0ull : 0ull;
             // the lane where this row's arcs begin in this step (lanes of one
-            // row are consecutive); a lane past the range is its own segment
-            const int32_t rs = rstart_off(rk) - base;
-            const int first = in ? (rs > 0 ? rs : 0) : al;
+            // row are consecutive: the nearest first arc at or below this
+            // lane, else lane 0); a lane past the range is its own segment
+            const uint64_t fb = (__ballot(in && (a & AROW_FIRST)) >> (h * AL)) & lane_mask_upto(al);
+            const int first = in ? (fb ? 63 - __builtin_clzll(fb) : 0) : al;
             load_words<WL>(cur + (size_t)u * W + hw, x);
 #pragma unroll
             for (int w = 0; w < WL; w++) x[w] &= hm;
             seg_or_scan<WL, AL>(x, al, first);
         }
         // the last lane of a row's run in this step
-        const bool tail = in && (al == AL - 1 || k + 1 == wb || k + 1 == re);
+        const bool tail = in && (al == AL - 1 || k + 1 == wb || last);
         if (tail && rk == crow) {
 #pragma unroll
             for (int w = 0; w < WL; w++) x[w] |= sm.wv.cacc[wv][hw + w];
         }
-        const bool closes = tail && k + 1 == re;            // the row's last arc in the tile
+        const bool closes = tail && last;                   // the row's last arc in the tile
         const bool leaves = tail && !closes && k + 1 == wb;  // open past this wave's range
         const bool carries = tail && !closes && !leaves;     // only the step's last arc
         if (closes) close_row(rk, x);
@@ -1020,8 +1040,6 @@ __device__ void pull_wave(PullSmem<W> &sm, const SlotArgs &s, const GraphArgs &g
             if (__builtin_amdgcn_readlane((int)f, AL - 1)) {
                 const int32_t cre = (int32_t)sm.rend[crow];
                 if (al == AL - 1) {
-                    if (h == 0)
-                        atomicOr(reinterpret_cast<unsigned long long *>(&sm.fin[crow >> 6]), 1ull << (crow & 63));
                     if (cre > wb) {
                         leave_row(crow, x);
                     } else if (rstart_off(crow) >= wa) {
