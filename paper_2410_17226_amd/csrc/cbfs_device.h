@@ -103,7 +103,15 @@ struct OutArgs {
     int32_t *status;          // [C]
     int32_t R;                // center-relative: the offset radius; min-relative: the diameter d
     int32_t minrel;           // 1: min-relative encode (P = d + 1), 0: center-relative (P = 2R + 1)
+    const int32_t *center;    // [C] each cluster's center vertex (the encode's radius check)
 };
+
+// Center-relative with R = 1: the encode needs no earlier round from dist.
+// A source's offset at any vertex is bounded by its distance to the center
+// (Section 3.1, Fact), so an offset outside [-1, 1] anywhere implies one at
+// the center itself, and the radius check is made there: bits reaching the
+// center after round 1 (finalize adds the sources that never reach it).
+__device__ __forceinline__ bool dist_free(const OutArgs &o) { return o.R == 1 && !o.minrel; }
 
 __host__ __device__ inline int64_t planes_of(const OutArgs &o)
 {
@@ -189,9 +197,13 @@ __host__ __device__ inline int32_t push_entries_per_block(int64_t pieces, int64_
 //     into place, and the positive planes are cleared for later rounds.
 //   - center not yet seen: dist holds the first round Delta_c any bit of the
 //     cluster arrived; for R >= 2 the bits are stashed at plane i - Delta_c.
-// Any bit whose offset leaves [-R, R] marks the cluster CBFS_E_RADIUS.
+// Any bit whose offset leaves [-R, R] marks the cluster CBFS_E_RADIUS.  For
+// R = 1 (dist_free) no earlier round is needed: the check is made at the
+// center (bits after round 1) and where bits come while earlier ones wait for
+// the center; dist is written once, when the center arrives.
 // dold is dist[c][v] as it stood before this call (the caller loads it with
-// the state words; only this call writes it in this round).
+// the state words; only this call writes it in this round; 0 and unused when
+// dist_free).
 // ---------------------------------------------------------------------------
 template <int WC>
 __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_t c, int32_t v,
@@ -236,6 +248,11 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
         return;
     }
     if (prev[0] & 1ull) {
+        if (R == 1) {
+            // the rest arrives one round after the center (plane 2 holds it)
+            if (i > 1 && v == o.center[c]) violate();
+            return;
+        }
         const int32_t k = i - (int32_t)dold;
         if (k < 1 || k > R) {
             violate();
@@ -245,7 +262,7 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
         return;
     }
     if (nw[0] & 1ull) {
-        const int32_t jc = any_prev ? i - (int32_t)dold : 0;
+        const int32_t jc = any_prev && R != 1 ? i - (int32_t)dold : 0;
         if (jc < 0 || jc > R) {
             violate();
             return;
@@ -274,6 +291,12 @@ __device__ __forceinline__ void emit_cluster(const OutArgs &o, int64_t n, int32_
         return;
     }
     // center not reached yet
+    if (R == 1) {
+        // bits seen in an earlier round are then two or more rounds ahead
+        // of the center; the first round itself is not needed
+        if (any_prev) violate();
+        return;
+    }
     int32_t j = 0;
     if (!any_prev) {
         *dslot = (uint32_t)i;
@@ -312,7 +335,7 @@ __device__ __forceinline__ void vertex_phase_cluster(const SlotArgs &s, const Gr
     const bool fields = WC == 1 && g.flog < 6;
     // a whole-word cluster's distance word is requested with the state words,
     // so the encode does not wait for a second round trip
-    const uint32_t dold = fields ? 0u : o.dist[(size_t)(g.c0 + j) * (size_t)n + (size_t)u];
+    const uint32_t dold = fields || dist_free(o) ? 0u : o.dist[(size_t)(g.c0 + j) * (size_t)n + (size_t)u];
     uint64_t cu[WC], sv[WC], nw[WC];
     uint64_t any = 0;
     const uint64_t am = active ? ~0ull : 0ull;  // a value mask, so the loads stay ahead of the test
@@ -349,7 +372,8 @@ __device__ __forceinline__ void vertex_phase_cluster(const SlotArgs &s, const Gr
         const uint64_t nf = (nw[0] >> sh) & fm;
         if (!nf) continue;
         const uint64_t pf = (sv[0] >> sh) & fm, ff = (g.full[j] >> sh) & fm;
-        emit_cluster<1>(o, n, c, u, round, &pf, &nf, &ff, o.dist[(size_t)c * (size_t)n + (size_t)u]);
+        emit_cluster<1>(o, n, c, u, round, &pf, &nf, &ff,
+                        dist_free(o) ? 0u : o.dist[(size_t)c * (size_t)n + (size_t)u]);
     }
 }
 

@@ -115,7 +115,7 @@ struct Plan {
     int64_t qcap = 0;
     int32_t total_sources = 0;
     // workspace offsets
-    size_t off_tiles_row = 0, off_tiles_edge = 0, off_cptr = 0, off_src = 0;
+    size_t off_tiles_row = 0, off_tiles_edge = 0, off_cptr = 0, off_src = 0, off_center = 0;
     size_t off_slotdesc = 0, off_groupdesc = 0, off_ctl = 0, off_stats = 0, off_hub = 0;
     size_t off_slots = 0, slot_bytes = 0;
     size_t total = 0;
@@ -236,6 +236,7 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
     p.off_tiles_edge = take(sizeof(int32_t) * (size_t)(p.ntiles + 1));
     p.off_cptr = take(sizeof(int32_t) * (size_t)(p.C + 1));
     p.off_src = take(sizeof(int32_t) * (size_t)std::max(1, p.total_sources));
+    p.off_center = take(sizeof(int32_t) * (size_t)p.C);
     p.off_slotdesc = take(sizeof(SlotArgs) * MAX_SLOTS);
     p.off_groupdesc = take(sizeof(GroupDesc) * (size_t)p.groups);
     p.off_ctl = take(sizeof(unsigned int) * CTL_WORDS + 512);
@@ -421,7 +422,7 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
     const GraphArgs gr = graph_args(p, g, ws);
     const int32_t *d_cptr = (const int32_t *)(ws + p.off_cptr);
     const int32_t *d_src = (const int32_t *)(ws + p.off_src);
-    OutArgs o{dist, masks, status, p.R, p.minrel};
+    OutArgs o{dist, masks, status, p.R, p.minrel, (const int32_t *)(ws + p.off_center)};
     hipError_t e;
     cbfs_run_stats &rs = g_last.host;
     const SlotArgs s = slot_at(p, ws, 0);
@@ -497,7 +498,7 @@ static cbfs_status run_persistent(const Plan &p, const cbfs_csr *g, uint32_t *di
     if (p.slots > blocks) return fail(CBFS_E_ARG, "cbfs_run_batch: more group slots than resident blocks");
     PersistArgs a{};
     a.gr = graph_args(p, g, ws);
-    a.o = OutArgs{dist, masks, status, p.R, p.minrel};
+    a.o = OutArgs{dist, masks, status, p.R, p.minrel, (const int32_t *)(ws + p.off_center)};
     a.slots = (const SlotArgs *)(ws + p.off_slotdesc);
     a.groups = (const GroupDesc *)(ws + p.off_groupdesc);
     a.num_groups = p.groups;
@@ -581,6 +582,8 @@ static cbfs_status run_batch_planned(const Plan &p, const cbfs_csr *g, const cbf
     std::vector<char> stage(hi - lo, 0);
     std::memcpy(stage.data() + (p.off_cptr - lo), b->cluster_ptr, sizeof(int32_t) * (size_t)(p.C + 1));
     std::memcpy(stage.data() + (p.off_src - lo), b->sources, sizeof(int32_t) * (size_t)p.total_sources);
+    for (int32_t c = 0; c < p.C; c++)
+        reinterpret_cast<int32_t *>(stage.data() + (p.off_center - lo))[c] = b->sources[b->cluster_ptr[c]];
     for (int32_t sl = 0; sl < p.slots; sl++) {
         SlotArgs s = slot_at(p, ws, sl);
         std::memcpy(stage.data() + (p.off_slotdesc - lo) + sizeof(SlotArgs) * sl, &s, sizeof(SlotArgs));
