@@ -410,6 +410,7 @@ def main():
     ap.add_argument("--group-words", type=int, default=0)
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--alpha", type=float, default=0.0, help="push/pull threshold (0 = library default)")
+    ap.add_argument("--beta", type=float, default=0.0, help="pull/push threshold (0 = library default)")
     ap.add_argument("--gamma", type=float, default=0.0, help="wave-form threshold (0 = library default)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -498,7 +499,7 @@ def main():
     rp_d = torch.from_numpy(rp).to(dev)
     col_d = torch.from_numpy(col).to(dev)
     tuning = P.Tuning(mode=args.mode, group_words=args.group_words, concurrent_groups=args.slots,
-                      alpha=args.alpha, gamma=args.gamma)
+                      alpha=args.alpha, beta=args.beta, gamma=args.gamma)
     tuned = None
     if args.tune:
         t0 = time.time()
