@@ -372,6 +372,42 @@ def _pll_batches(count, first=200, growth=1.5, max_batch=1000):
     return out
 
 
+def gather_ceiling(torch, col_d, n, m, reps=5, blocks=4096):
+    """Time of one pass that gathers, for every arc of the CSR in CSR order, a row of 64, 128
+    or 256 bytes (the pull's arc-phase traffic with none of its other work), measured with the
+    probe kernel of ``libcbfs_probe.so``: the floor for a pull round that gathers every arc's set."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2410_17226_amd", "libcbfs_probe.so"))
+    lib.cbfs_probe_gather.restype = ctypes.c_int
+    lib.cbfs_probe_gather.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    assert col_d.dtype == torch.int32 and col_d.is_contiguous() and col_d.numel() == m
+    stream = torch.cuda.current_stream()
+    out = torch.empty(blocks * 256, dtype=torch.int64, device=col_d.device)
+    res = {}
+    for row in (64, 128, 256):
+        state = torch.ones((n, row // 8), dtype=torch.int64, device=col_d.device)
+
+        def once():
+            rc = lib.cbfs_probe_gather(row, col_d.data_ptr(), m, state.data_ptr(), out.data_ptr(), blocks,
+                                       stream.cuda_stream)
+            if rc != 0:
+                raise RuntimeError(f"gather probe launch failed ({rc})")
+        once()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            once()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[str(row)] = round(e0.elapsed_time(e1) / reps, 3)
+        del state
+    return {"pass_ms": res, "row_bytes": [64, 128, 256],
+            "note": "one pass over all arcs in CSR order gathering a row of each size per arc (probe kernel, "
+                    "no other work): the floor for a pull round that gathers every arc's set"}
+
+
 def rmat14_latency(P, torch, dev):
     """The one-cluster R-MAT scale-14 workload: time of one cbfs_run_batch
     (median of 20 after 3 warm-ups), graph and outputs resident."""
@@ -416,6 +452,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-clusters", type=int, default=6, help="clusters in the CPU oracle sample")
     ap.add_argument("--no-query", action="store_true")
+    ap.add_argument("--no-gather-ceiling", action="store_true", help="skip the gather-probe floor of the pull")
     ap.add_argument("--workload", default="rmat22", choices=["rmat22", "grid4096", "chunglu25", "rmat14"],
                     help="batch workload (the default is the headline one)")
     ap.add_argument("--no-rmat14", action="store_true", help="skip the one-cluster R-MAT 14 latency figure")
@@ -572,6 +609,10 @@ def main():
                 "bytes_per_launch": int(per_launch), "avg_launch_ms": round(avg_ms, 3), "launches": launches,
                 "units": unit_note, "step_algorithmic_bytes": int(B_alg_step),
                 "step_frac": round(B_alg_step / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    if not args.no_gather_ceiling:
+        roofline["gather_ceiling"] = gather_ceiling(torch, col_d, n, m)
+        print(f"[bench] gather ceiling: {roofline['gather_ceiling']['pass_ms']}", file=sys.stderr, flush=True)
 
     # plain form: one cluster per call, same kernels and defaults
     plain = None

@@ -10,6 +10,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcbfs.so")
 SOURCES = ["cbfs_run.hip", "cbfs_kernels.hip", "cbfs_query.hip", "cbfs_pll.hip", "cbfs_graph.cpp"]
+# measurement only (bench.py --gather-ceiling): not linked into libcbfs
+PROBE_SOURCE = "probe_gather.hip"
+PROBE_LIB = os.path.join(HERE, "libcbfs_probe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -22,10 +25,14 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source into ``paper_2410_17226_amd/libcbfs.so`` (always rebuilds)."""
+    """Compile every source into ``paper_2410_17226_amd/libcbfs.so`` and the gather probe into
+    ``libcbfs_probe.so`` (always rebuilds)."""
     tmp = LIB + ".tmp"
     objs = []
     procs = []
+    probe_tmp = PROBE_LIB + ".tmp"
+    probe_cmd = [HIPCC] + FLAGS + ["-x", "hip", os.path.join(CSRC, PROBE_SOURCE), "-o", probe_tmp]
+    procs.append((PROBE_SOURCE, subprocess.Popen(probe_cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(CSRC, "_build", src + ".o")
@@ -52,6 +59,7 @@ def build(verbose: bool = False) -> str:
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    os.replace(probe_tmp, PROBE_LIB)
     return LIB
 
 

@@ -32,6 +32,13 @@ def test_library_exports_every_declared_symbol():
     assert sorted(B.SYMBOLS) == declared
 
 
+def test_gather_probe_is_a_separate_library():
+    # the measurement probe of bench.py is built beside libcbfs, not into it
+    probe = ctypes.CDLL(os.path.join(ROOT, "paper_2410_17226_amd", "libcbfs_probe.so"))
+    assert hasattr(probe, "cbfs_probe_gather")
+    assert "cbfs_probe_gather" not in P.exported_symbols()
+
+
 def test_status_strings():
     assert P.status_string(0) == "CBFS_OK"
     assert P.status_string(-5) == "CBFS_E_RADIUS"
