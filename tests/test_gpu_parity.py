@@ -168,6 +168,57 @@ def test_parity_disconnected_and_violations():
         assert_same(gpu_cbfs(rp, col, cp1, src1, 1), oracle.cbfs(orp, ocol, cp1, src1, R=1), "isolated")
 
 
+@pytest.mark.parametrize("tun", [None, dict(force_pull=1, gamma=1e-9), dict(alpha=-1.0), dict(mode=1, group_words=16),
+                                 dict(mode=2, concurrent_groups=3), dict(mode=2, group_words=1, concurrent_groups=5),
+                                 dict(field_bits=8)],
+                         ids=["default", "pull", "push", "w16", "pers", "pers_w1", "fields8"])
+def test_parity_radius_one_violation_two_hops_out(tun):
+    """R = 1 with one source exactly two hops from its center: the only offsets
+    outside [-1, 1] are +2 at the center and -2 at that source (the encode checks
+    the center), next to valid clusters of the same centers; and a source in
+    another component, which never reaches the center (found at finalize)."""
+    import paper_2410_17226_amd as P
+    n, s, d = synth.random_graph(160, 0.03, 23)
+    rp, col, _ = P.build_csr(n, s, d, flags=7)
+    nv = rp.size - 1
+    deg = np.diff(rp)
+
+    def hops_from(c):
+        dist = np.full(nv, -1)
+        dist[c] = 0
+        frontier = [c]
+        while frontier:
+            nxt = []
+            for u in frontier:
+                for w in col[rp[u]:rp[u + 1]]:
+                    if dist[w] < 0:
+                        dist[w] = dist[u] + 1
+                        nxt.append(w)
+            frontier = nxt
+        return dist
+
+    cps, srcs = [0], []
+    for c in np.argsort(-deg, kind="stable")[:6]:
+        h = hops_from(c)
+        nb = col[rp[c]:rp[c + 1]][:8].tolist()
+        two = np.nonzero(h == 2)[0]
+        far = np.nonzero(h < 0)[0]
+        srcs += [int(c)] + nb                       # valid
+        cps.append(len(srcs))
+        if two.size:
+            srcs += [int(c)] + nb + [int(two[0])]   # one source two hops out
+            cps.append(len(srcs))
+        if far.size:
+            srcs += [int(c)] + nb[:2] + [int(far[0])]  # one source the center never reaches
+            cps.append(len(srcs))
+    cp = np.array(cps, np.int32)
+    src = np.array(srcs, np.int32)
+    gpu = gpu_cbfs(rp, col, cp, src, 1, tuning_of(tun, 1, int(np.diff(cp).max())))
+    ref = oracle.cbfs(rp, col, cp, src, R=1)
+    assert (ref[2] == oracle.E_RADIUS).sum() >= 6 and (ref[2] == 0).sum() == 6
+    assert_same(gpu, ref, f"two hops out, {tun}")
+
+
 def test_parity_radius_zero():
     """R = 0: single-source clusters (plain BFS) and a two-source cluster that
     violates the radius, in every direction mode."""
