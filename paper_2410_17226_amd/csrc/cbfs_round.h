@@ -72,11 +72,18 @@ template <int W>
 __device__ __forceinline__ void init_part(const SlotArgs &s, int64_t n, const GroupDesc &g, const OutArgs &o,
                                           int64_t tid, int64_t stride)
 {
+    // 16-byte stores (the arrays start 256-byte aligned in the workspace)
     const int64_t words = n * W;
-    for (int64_t k = tid; k < words; k += stride) {
-        s.A[k] = 0;
-        s.B[k] = 0;
-        s.seen[k] = 0;
+    const ulonglong2 z = make_ulonglong2(0ull, 0ull);
+    for (int64_t k = tid; k < (words >> 1); k += stride) {
+        reinterpret_cast<ulonglong2 *>(s.A)[k] = z;
+        reinterpret_cast<ulonglong2 *>(s.B)[k] = z;
+        reinterpret_cast<ulonglong2 *>(s.seen)[k] = z;
+    }
+    if ((words & 1) && tid == 0) {
+        s.A[words - 1] = 0;
+        s.B[words - 1] = 0;
+        s.seen[words - 1] = 0;
     }
     for (int64_t k = tid; k < s.nwords; k += stride) {
         s.bits0[k] = 0;
@@ -132,8 +139,14 @@ __device__ void seed_block(Stager<STAGE_CAP> &st, const SlotArgs &s, const Graph
     const int32_t total = cluster_ptr[g.c0 + g.nc] - first;
     for (int32_t k = threadIdx.x; k < total; k += BLOCK) {
         const int32_t idx = first + k;
-        int32_t j = 0;
-        while (cluster_ptr[g.c0 + j + 1] <= idx) j++;
+        // the cluster j holding source idx (clusters are non-empty, so the
+        // group's cluster_ptr entries increase strictly)
+        int32_t j = 0, jh = g.nc - 1;
+        while (j < jh) {
+            const int32_t mid = (j + jh + 1) >> 1;
+            if (cluster_ptr[g.c0 + mid] <= idx) j = mid;
+            else jh = mid - 1;
+        }
         const int32_t i = idx - cluster_ptr[g.c0 + j];
         const int32_t v = sources[idx];
         if (WC == 1 && g.flog < 6) {  // cluster j in field j % F of word j / F
@@ -300,31 +313,24 @@ __device__ void push_hub_block(HubSmem<W> &sm, const SlotArgs &s, const GraphArg
     if ((int)threadIdx.x < nh) {
         const int32_t u = hubs[threadIdx.x];
         const int32_t rs = gr.row_ptr[u], re = gr.row_ptr[u + 1];
-        // the first arcs with id >= v0 and >= v1: both searches at once, each
-        // round probing 4 points per bracket (8 loads in flight), so a list of
-        // d arcs takes about log5(d) dependent rounds
+        // the first arcs with id >= v0 and >= v1: two binary searches side by
+        // side (two loads in flight per round).  With a few hundred blocks
+        // resident the searches are bound by the number of loads, so one probe
+        // per bracket beats wider fan-outs (4 probes: +13 %, 8: +35 %)
         int32_t lo[2] = {rs, rs}, hi[2] = {re, re};
         const int32_t key[2] = {(int32_t)v0, v1};
         while (lo[0] < hi[0] || lo[1] < hi[1]) {
-            int32_t q[2][4], x[2][4];
+            int32_t q[2], x[2];
 #pragma unroll
-            for (int h = 0; h < 2; h++)
-#pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    q[h][j] = lo[h] + (int32_t)(((int64_t)(hi[h] - lo[h]) * (j + 1)) / 5);
-                    x[h][j] = lo[h] < hi[h] ? gr.col[q[h][j]] : 0;
-                }
+            for (int h = 0; h < 2; h++) {
+                q[h] = lo[h] + ((hi[h] - lo[h]) >> 1);
+                x[h] = lo[h] < hi[h] ? gr.col[q[h]] : 0;
+            }
 #pragma unroll
             for (int h = 0; h < 2; h++) {
                 if (lo[h] >= hi[h]) continue;
-                int32_t nlo = lo[h], nhi = hi[h];
-#pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    if (x[h][j] < key[h]) nlo = q[h][j] + 1 > nlo ? q[h][j] + 1 : nlo;
-                    else nhi = q[h][j] < nhi ? q[h][j] : nhi;
-                }
-                lo[h] = nlo;
-                hi[h] = nhi;
+                if (x[h] < key[h]) lo[h] = q[h] + 1;
+                else hi[h] = q[h];
             }
         }
         len = lo[1] - lo[0];
