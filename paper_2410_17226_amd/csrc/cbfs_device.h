@@ -48,6 +48,7 @@ enum { PULL_WALK = 0, PULL_WAVE = 1 };  // forms of the pull round
 constexpr int HUB_MAX = 256;        // frontier vertices of a range-owned push round at most
 constexpr int HUB_RANGE = 256;      // target vertices owned by one range-owned push block
 constexpr int STAGE_CAP = 1024;     // LDS frontier staging capacity per push/seed block
+constexpr int SEED_PER_BLOCK = 64;  // sources per block of a seed launch
 // arcs per pass when each push thread walks its own entry (wide groups hold
 // fewer neighbour sets in registers)
 template <int W>

@@ -46,7 +46,7 @@ hipError_t launch_tiles(const int32_t *row_ptr, int64_t n, int64_t m, int32_t nt
                         int32_t *tile_edge, hipStream_t st);
 hipError_t launch_init(int W, const SlotArgs &s, int64_t n, const GroupDesc &g, const OutArgs &o, hipStream_t st);
 hipError_t launch_seed(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                       const int32_t *sources, const int32_t *cluster_ptr, hipStream_t st);
+                       const int32_t *sources, const int32_t *cluster_ptr, int32_t num_sources, hipStream_t st);
 hipError_t launch_push(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                        const OutArgs &o, int32_t round, int64_t nq, int64_t degsum, hipStream_t st);
 // Push round for a frontier of at most HUB_MAX vertices (nq queue entries):

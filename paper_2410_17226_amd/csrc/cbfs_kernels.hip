@@ -50,7 +50,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed(SlotArgs s, GraphArgs gr, GroupD
                                                 const int32_t *cluster_ptr)
 {
     __shared__ Stager<STAGE_CAP> st;
-    seed_block<W, WC>(st, s, gr, g, sources, cluster_ptr);
+    seed_block<W, WC>(st, s, gr, g, sources, cluster_ptr, blockIdx.x, gridDim.x, SEED_PER_BLOCK);
 }
 
 template <int W, int WC>
@@ -484,9 +484,10 @@ hipError_t launch_init(int W, const SlotArgs &s, int64_t n, const GroupDesc &g, 
 }
 
 hipError_t launch_seed(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                       const int32_t *sources, const int32_t *cluster_ptr, hipStream_t st)
+                       const int32_t *sources, const int32_t *cluster_ptr, int32_t num_sources, hipStream_t st)
 {
-    CBFS_DISPATCH(W, WC, (k_seed<W, WC><<<1, BLOCK, 0, st>>>(s, gr, g, sources, cluster_ptr)));
+    const int blocks = std::max(1, (num_sources + SEED_PER_BLOCK - 1) / SEED_PER_BLOCK);
+    CBFS_DISPATCH(W, WC, (k_seed<W, WC><<<blocks, BLOCK, 0, st>>>(s, gr, g, sources, cluster_ptr)));
     return hipGetLastError();
 }
 

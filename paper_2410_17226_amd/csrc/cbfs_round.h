@@ -130,14 +130,18 @@ __device__ __forceinline__ void clear_item(const SlotArgs &s, int32_t round, boo
 // F_0 = the sources.  sources/cluster_ptr are the batch arrays on the device.
 template <int W, int WC>
 __device__ void seed_block(Stager<STAGE_CAP> &st, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                           const int32_t *sources, const int32_t *cluster_ptr)
+                           const int32_t *sources, const int32_t *cluster_ptr, int32_t part = 0, int32_t parts = 1,
+                           int32_t per = BLOCK)
 {
     __syncthreads();
     stager_init(st);
     __syncthreads();
     const int32_t first = cluster_ptr[g.c0];
     const int32_t total = cluster_ptr[g.c0 + g.nc] - first;
-    for (int32_t k = threadIdx.x; k < total; k += BLOCK) {
+    // block `part` of `parts` takes every parts-th run of `per` sources (the
+    // whole block then writes the pieces of the hubs among them); a source in
+    // several clusters is claimed, and queued, once: by the bitmap
+    for (int32_t k = part * per + (int32_t)threadIdx.x; (int32_t)threadIdx.x < per && k < total; k += parts * per) {
         const int32_t idx = first + k;
         // the cluster j holding source idx (clusters are non-empty, so the
         // group's cluster_ptr entries increase strictly)

@@ -431,7 +431,8 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
         const GroupDesc gd = group_desc(p, b, grp);
         if ((e = PROF(CBFS_KERNEL_INIT, st, launch_init(p.W, s, p.n, gd, o, st))) != hipSuccess)
             return hip_fail("init", e);
-        if ((e = PROF(CBFS_KERNEL_SEED, st, launch_seed(p.W, p.WC, s, gr, gd, d_src, d_cptr, st))) != hipSuccess)
+        const int32_t nsrc = b->cluster_ptr[gd.c0 + gd.nc] - b->cluster_ptr[gd.c0];
+        if ((e = PROF(CBFS_KERNEL_SEED, st, launch_seed(p.W, p.WC, s, gr, gd, d_src, d_cptr, nsrc, st))) != hipSuccess)
             return hip_fail("seed", e);
         bool dense = false;
         int32_t pulls = 0;
