@@ -47,6 +47,12 @@ static_assert(PULL_CLAIM_WORDS <= BLOCK, "one claimed word per thread at a pull 
 enum { PULL_WALK = 0, PULL_WAVE = 1 };  // forms of the pull round
 constexpr int HUB_MAX = 256;        // frontier vertices of a range-owned push round at most
 constexpr int HUB_RANGE = 256;      // target vertices owned by one range-owned push block
+constexpr int HUB_RANGE_LOG = 8;
+static_assert(HUB_RANGE == 1 << HUB_RANGE_LOG, "HUB_RANGE_LOG is log2 of HUB_RANGE");
+constexpr int HB_CHUNK = 4096;      // arcs per block of the slice-bounds pass
+// row length of the range-owned push's slice-bounds table: one entry per owned
+// range and one past the last
+__host__ __device__ inline int64_t hub_bounds_stride(int64_t n) { return (n + HUB_RANGE - 1) / HUB_RANGE + 1; }
 constexpr int STAGE_CAP = 1024;     // LDS frontier staging capacity per push/seed block
 constexpr int SEED_PER_BLOCK = 64;  // sources per block of a seed launch
 // arcs per pass when each push thread walks its own entry (wide groups hold

@@ -53,7 +53,8 @@ hipError_t launch_push(int W, int WC, const SlotArgs &s, const GraphArgs &gr, co
 // lists them into hubs[0 .. hubs[HUB_MAX]) (HUB_MAX + 1 ints of device
 // memory), then one block per HUB_RANGE target vertices.
 hipError_t launch_push_hub(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                           const OutArgs &o, int32_t round, int64_t nq, int32_t *hubs, hipStream_t st);
+                           const OutArgs &o, int32_t round, int64_t nq, int64_t degsum, int32_t *hubs,
+                           int32_t *bounds, hipStream_t st);
 hipError_t launch_pull(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
                        const OutArgs &o, int32_t round, int32_t form, bool queue, hipStream_t st);
 // The queue of F_round from its bitmap (after rounds that left only the

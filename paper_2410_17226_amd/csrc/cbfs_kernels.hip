@@ -75,13 +75,20 @@ __global__ __launch_bounds__(BLOCK) void k_hub_list(SlotArgs s, int32_t round, i
     if (slot < HUB_MAX) hubs[slot] = (int32_t)(e & 0xffffffff);
 }
 
+__global__ __launch_bounds__(BLOCK) void k_hub_bounds(GraphArgs gr, const int32_t *hubs, int32_t *bounds,
+                                                      int64_t stride)
+{
+    __shared__ HubBoundsSmem sm;
+    hub_bounds_block(sm, gr, hubs, bounds, stride);
+}
+
 template <int W, int WC>
 __global__ __launch_bounds__(BLOCK) void k_push_hub(SlotArgs s, GraphArgs gr, GroupDesc g, OutArgs o, int32_t round,
-                                                    const int32_t *hubs)
+                                                    const int32_t *hubs, const int32_t *bounds, int64_t stride)
 {
     __shared__ HubSmem<W> sm;
     clear_ahead_part(s, round, (int64_t)blockIdx.x * BLOCK + threadIdx.x, (int64_t)gridDim.x * BLOCK);
-    push_hub_block<W, WC>(sm, s, gr, g, o, round, hubs, blockIdx.x);
+    push_hub_block<W, WC>(sm, s, gr, g, o, round, hubs, bounds, stride, blockIdx.x);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_bits_to_queue(SlotArgs s, GraphArgs gr, int32_t fround, int32_t what)
@@ -502,7 +509,8 @@ hipError_t launch_push(int W, int WC, const SlotArgs &s, const GraphArgs &gr, co
 }
 
 hipError_t launch_push_hub(int W, int WC, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                           const OutArgs &o, int32_t round, int64_t nq, int32_t *hubs, hipStream_t st)
+                           const OutArgs &o, int32_t round, int64_t nq, int64_t degsum, int32_t *hubs,
+                           int32_t *bounds, hipStream_t st)
 {
     // the host guarantees at most HUB_MAX frontier vertices
     hipError_t e = hipMemsetAsync(hubs + HUB_MAX, 0, sizeof(int32_t), st);
@@ -511,8 +519,15 @@ hipError_t launch_push_hub(int W, int WC, const SlotArgs &s, const GraphArgs &gr
         k_hub_list<<<(unsigned)((nq + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(s, round, nq, hubs);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    // the slice starts of every (frontier vertex, owned range); the blocks
+    // stride over the arcs, so the degree sum only sizes the grid
+    const int64_t stride = hub_bounds_stride(gr.n);
+    const int64_t bb = std::min<int64_t>(std::max<int64_t>(1, (degsum + HB_CHUNK - 1) / HB_CHUNK), 4096);
+    k_hub_bounds<<<(unsigned)bb, BLOCK, 0, st>>>(gr, hubs, bounds, stride);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t blocks = std::max<int64_t>((gr.n + HUB_RANGE - 1) / HUB_RANGE, clear_blocks(s.nwords));
-    CBFS_DISPATCH(W, WC, (k_push_hub<W, WC><<<(unsigned)blocks, BLOCK, 0, st>>>(s, gr, g, o, round, hubs)));
+    CBFS_DISPATCH(W, WC, (k_push_hub<W, WC><<<(unsigned)blocks, BLOCK, 0, st>>>(s, gr, g, o, round, hubs, bounds,
+                                                                                 stride)));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t per_block = (int64_t)BLOCK * BQ_VPT;
     k_bits_to_queue<<<(unsigned)((gr.n + per_block - 1) / per_block), BLOCK, 0, st>>>(s, gr, round + 1, BITS_COUNT);

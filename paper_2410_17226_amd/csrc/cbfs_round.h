@@ -277,8 +277,9 @@ __device__ void push_chunk(PushSmem<W> &sm, const SlotArgs &s, const GraphArgs &
 // Round i, push direction, for a frontier of at most HUB_MAX vertices whose
 // arcs are many (on skewed graphs the sources of round 0 are hubs whose
 // neighbour lists overlap).  Each block owns HUB_RANGE consecutive target
-// vertices.  For every frontier vertex u it finds the slice of u's sorted
-// neighbour list inside its range (two binary searches), ORs Seen_i(u) into
+// vertices.  For every frontier vertex u it reads the slice of u's sorted
+// neighbour list inside its range (from the table of hub_bounds_block, built
+// by a pass over the frontier's arcs just before), ORs Seen_i(u) into
 // LDS sets of its targets, and then writes nxt(v) once per target with a plain
 // store: the global set-union atomics of the arc-parallel push become LDS
 // atomics, and a target hit by many frontier vertices is written once.  A
@@ -292,6 +293,54 @@ static_assert(WAVES * 4 + 4 <= 64, "the merges after a wave-form pass run in wav
 static_assert(HUB_RANGE == BLOCK && HUB_MAX <= BLOCK, "one owned target and one frontier vertex per thread");
 static_assert(HUB_RANGE % 64 == 0, "a block owns whole frontier-bitmap words");
 
+// Slice starts for the range-owned push.  For frontier vertex h (hubs[h])
+// and each owned range b up to the range of its last arc, bounds[h * stride +
+// b] is the first arc of h's sorted neighbour list whose target is >= b *
+// HUB_RANGE.  One thread per arc of the concatenated lists: an arc whose range
+// differs from its predecessor's writes the entries of the ranges from the
+// one after the predecessor's up to its own (every entry has one writer); the
+// push takes ranges past the last arc as starting at the list's end.  Blocks
+// stride over chunks of HB_CHUNK arcs, so any grid covers every arc.
+struct HubBoundsSmem {
+    int32_t rs[HUB_MAX], pre[HUB_MAX + 1];
+    int tmp[WAVES + 1];
+};
+
+__device__ void hub_bounds_block(HubBoundsSmem &sm, const GraphArgs &gr, const int32_t *hubs, int32_t *bounds,
+                                 int64_t stride)
+{
+    const int32_t nh = hubs[HUB_MAX] < HUB_MAX ? hubs[HUB_MAX] : HUB_MAX;
+    int32_t d = 0;
+    if ((int)threadIdx.x < nh) {
+        const int32_t u = hubs[threadIdx.x];
+        const int32_t rs = gr.row_ptr[u];
+        d = gr.row_ptr[u + 1] - rs;
+        sm.rs[threadIdx.x] = rs;
+    }
+    int total;
+    const int off = block_exclusive_scan(d, sm.tmp, &total);
+    if ((int)threadIdx.x < nh) sm.pre[threadIdx.x] = off;
+    __syncthreads();
+    for (int64_t c0 = (int64_t)blockIdx.x * HB_CHUNK; c0 < total; c0 += (int64_t)gridDim.x * HB_CHUNK) {
+        const int32_t c1 = (int32_t)(c0 + HB_CHUNK < total ? c0 + HB_CHUNK : total);
+        for (int32_t q = (int32_t)c0 + (int32_t)threadIdx.x; q < c1; q += BLOCK) {
+            // the list holding arc q: the last h with pre[h] <= q (an empty
+            // list shares its start with the next one, which wins)
+            int lo = 0, hi = nh;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (sm.pre[mid] <= q) lo = mid;
+                else hi = mid;
+            }
+            const int32_t e = sm.rs[lo] + (q - sm.pre[lo]);
+            const int32_t r = gr.col[e] >> HUB_RANGE_LOG;
+            const int32_t prev = q == sm.pre[lo] ? -1 : (gr.col[e - 1] >> HUB_RANGE_LOG);
+            int32_t *bh = bounds + (size_t)lo * (size_t)stride;
+            for (int32_t b = prev + 1; b <= r; b++) bh[b] = e;
+        }
+    }
+}
+
 template <int W>
 struct HubSmem {
     uint64_t acc[HUB_RANGE * W];  // OR of the frontier sets arriving at each owned target
@@ -301,7 +350,8 @@ struct HubSmem {
 
 template <int W, int WC>
 __device__ void push_hub_block(HubSmem<W> &sm, const SlotArgs &s, const GraphArgs &gr, const GroupDesc &g,
-                               const OutArgs &o, int32_t round, const int32_t *hubs, int64_t b)
+                               const OutArgs &o, int32_t round, const int32_t *hubs, const int32_t *bounds,
+                               int64_t stride, int64_t b)
 {
     const int64_t v0 = b * HUB_RANGE;
     if (v0 >= gr.n) return;  // block-uniform
@@ -317,29 +367,16 @@ __device__ void push_hub_block(HubSmem<W> &sm, const SlotArgs &s, const GraphArg
     if ((int)threadIdx.x < nh) {
         const int32_t u = hubs[threadIdx.x];
         const int32_t rs = gr.row_ptr[u], re = gr.row_ptr[u + 1];
-        // the first arcs with id >= v0 and >= v1: two binary searches side by
-        // side (two loads in flight per round).  With a few hundred blocks
-        // resident the searches are bound by the number of loads, so one probe
-        // per bracket beats wider fan-outs (4 probes: +13 %, 8: +35 %)
-        int32_t lo[2] = {rs, rs}, hi[2] = {re, re};
-        const int32_t key[2] = {(int32_t)v0, v1};
-        while (lo[0] < hi[0] || lo[1] < hi[1]) {
-            int32_t q[2], x[2];
-#pragma unroll
-            for (int h = 0; h < 2; h++) {
-                q[h] = lo[h] + ((hi[h] - lo[h]) >> 1);
-                x[h] = lo[h] < hi[h] ? gr.col[q[h]] : 0;
-            }
-#pragma unroll
-            for (int h = 0; h < 2; h++) {
-                if (lo[h] >= hi[h]) continue;
-                if (x[h] < key[h]) lo[h] = q[h] + 1;
-                else hi[h] = q[h];
-            }
-        }
-        len = lo[1] - lo[0];
+        // the slice [first arc >= v0, first arc >= v1) from the bounds table
+        // (hub_bounds_block); ranges past the list's last arc have no entry
+        // there and start at re
+        const int32_t last = re > rs ? (gr.col[re - 1] >> HUB_RANGE_LOG) : -1;
+        const int32_t *bh = bounds + (size_t)threadIdx.x * (size_t)stride;
+        const int32_t lo0 = b <= last ? bh[b] : re;
+        const int32_t lo1 = b + 1 <= last ? bh[b + 1] : re;
+        len = lo1 - lo0;
         sm.hub[threadIdx.x] = u;
-        sm.hlo[threadIdx.x] = lo[0];
+        sm.hlo[threadIdx.x] = lo0;
     }
     int total;
     const int off = block_exclusive_scan(len, sm.tmp, &total);

@@ -116,7 +116,7 @@ struct Plan {
     int32_t total_sources = 0;
     // workspace offsets
     size_t off_tiles_row = 0, off_tiles_edge = 0, off_cptr = 0, off_src = 0, off_center = 0;
-    size_t off_slotdesc = 0, off_groupdesc = 0, off_ctl = 0, off_stats = 0, off_hub = 0;
+    size_t off_slotdesc = 0, off_groupdesc = 0, off_ctl = 0, off_stats = 0, off_hub = 0, off_hubbounds = 0;
     size_t off_slots = 0, slot_bytes = 0;
     size_t total = 0;
 };
@@ -242,6 +242,7 @@ static cbfs_status make_plan(const cbfs_csr *g, const cbfs_batch *b, const cbfs_
     p.off_ctl = take(sizeof(unsigned int) * CTL_WORDS + 512);
     p.off_stats = take(sizeof(long long) * STAT_WORDS * (size_t)p.groups);
     p.off_hub = take(sizeof(int32_t) * (HUB_MAX + 1));
+    p.off_hubbounds = take(sizeof(int32_t) * (size_t)HUB_MAX * (size_t)hub_bounds_stride(p.n));
     p.off_slots = off;
     size_t sb = 0;
     sb += 3 * align_up(sizeof(uint64_t) * (size_t)p.n * p.W);
@@ -478,7 +479,8 @@ static cbfs_status run_host_loop(const Plan &p, const cbfs_csr *g, const cbfs_ba
             if (dense) e = PROF(CBFS_KERNEL_PULL, st, launch_pull(p.W, p.WC, s, gr, gd, o, round, form, false, st));
             else if (hub)
                 e = PROF(CBFS_KERNEL_PUSH, st,
-                         launch_push_hub(p.W, p.WC, s, gr, gd, o, round, pieces, (int32_t *)(ws + p.off_hub), st));
+                         launch_push_hub(p.W, p.WC, s, gr, gd, o, round, pieces, degsum, (int32_t *)(ws + p.off_hub),
+                                         (int32_t *)(ws + p.off_hubbounds), st));
             else e = PROF(CBFS_KERNEL_PUSH, st, launch_push(p.W, p.WC, s, gr, gd, o, round, pieces, degsum, st));
             if (e != hipSuccess) return hip_fail(dense ? "pull" : "push", e);
         }
