@@ -154,7 +154,7 @@ def test_parity_disconnected_and_violations():
     centers = np.nonzero(deg > 0)[0][:12].astype(np.int32)
     cp, src = P.select_clusters(rp, col, centers, 64, 2)   # radius-2 clusters ...
     for R in (1, 2):                                        # ... violate R = 1
-        for tun in (None, dict(force_pull=1), dict(alpha=-1.0)):
+        for tun in (None, dict(force_pull=1), dict(alpha=-1.0), dict(mode=1, alpha=-1.0, hub_arcs=1)):
             gpu = gpu_cbfs(rp, col, cp, src, R, tuning_of(tun))
             ref = oracle.cbfs(orp, ocol, cp, src, R=R)
             assert_same(gpu, ref, f"R={R} {tun}")
@@ -166,6 +166,12 @@ def test_parity_disconnected_and_violations():
         cp1 = np.array([0, 1], np.int32)
         src1 = iso[:1].astype(np.int32)
         assert_same(gpu_cbfs(rp, col, cp1, src1, 1), oracle.cbfs(orp, ocol, cp1, src1, R=1), "isolated")
+        # an isolated source next to a connected one in one range-owned push
+        # round (a frontier list of no arcs beside a list with arcs)
+        cp2 = np.array([0, 2], np.int32)
+        src2 = np.array([centers[0], iso[0]], np.int32)
+        hub = P.Tuning(mode=1, alpha=-1.0, hub_arcs=1)
+        assert_same(gpu_cbfs(rp, col, cp2, src2, 1, hub), oracle.cbfs(orp, ocol, cp2, src2, R=1), "isolated, hub push")
 
 
 @pytest.mark.parametrize("tun", [None, dict(force_pull=1, gamma=1e-9), dict(alpha=-1.0), dict(mode=1, group_words=16),
